@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark: speculative iterative colouring of R-MAT scale 24 on one MI355X.
+
+A step is one full colouring (every round, to an empty worklist) of a graph
+already resident in HBM, through the C ABI.  Prints one JSON line with
+edges coloured per second, the roofline of the dominant kernel, the CPU
+oracle's throughput on the same workload, and the colour counts of the GPU
+result and of serial greedy.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--order natural|perm] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+WORKLOADS = {
+    # name: (kind, params)
+    "rmat24": ("rmat", dict(scale=24, edge_factor=8, abcd=(0.55, 0.1, 0.1, 0.25), seed=11)),
+    "rmat20-er": ("rmat", dict(scale=20, edge_factor=8, abcd=(0.25, 0.25, 0.25, 0.25), seed=11)),
+    "rmat20-g": ("rmat", dict(scale=20, edge_factor=8, abcd=(0.45, 0.15, 0.15, 0.25), seed=11)),
+    "uniform14": ("uniform", dict(n=1 << 14, samples=1 << 17, seed=1)),
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_graph(name):
+    import graphgen
+    kind, p = WORKLOADS[name]
+    if kind == "rmat":
+        return graphgen.rmat(p["scale"], p["edge_factor"], p["abcd"][:3], p["seed"])
+    return graphgen.uniform(p["n"], p["samples"], p["seed"])
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1205_3809_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith(".hip"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def load_traffic(workload, order, kernel, launches):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--order", default="natural", choices=["natural", "perm"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timed pass")
+    ap.add_argument("--engine", default="incremental", choices=["incremental", "plain"])
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
+              "sharding of the method is described in the design notes but not built." % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1205_3809_amd as gc
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+
+    t0 = time.time()
+    g = make_graph(args.workload)
+    key = graphgen.random_priority(g.n, 12) if args.order == "perm" else None
+    log("graph %s n=%d nnz=%d edges=%d built in %.1fs" % (args.workload, g.n, g.nnz, g.edges, time.time() - t0))
+
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    pr = None if key is None else torch.from_numpy(key.view(np.int32)).to(dev)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    # one run with statistics: rounds, colours, per-round worklist and edge work
+    flags = gc.FLAG_PLAIN if args.engine == "plain" else 0
+    _, st = gc.color_graph_ex(rp, ci, pr, out, flags=flags, stats=True, max_log=1 << 16)
+    torch.cuda.synchronize()
+    gpu_colors = out.cpu().numpy()
+    log("rounds=%d colours=%d edge_work=%.2f x nnz" % (st.rounds, st.num_colors, st.edge_work / max(g.nnz, 1)))
+
+    def step():
+        if flags:
+            gc.color_graph_ex(rp, ci, pr, out, flags=flags)
+        else:
+            gc.color_graph(rp, ci, pr, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K full colourings
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_per_step = 1000.0 * wall / args.steps
+    log("timed %d steps: %.3f ms/step (wall), %.3f ms/step (events)"
+        % (args.steps, ms_per_step, ev0.elapsed_time(ev1) / args.steps))
+    edges_per_s = g.edges / (ms_per_step / 1000.0)
+
+    # per-kernel durations: HIP events around every launch, same steps again
+    roofline = None
+    kern = {}
+    if not args.no_profile:
+        gc.profile(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        if args.engine == "plain":
+            kinds = (("phase1", gc.PROF_PHASE1), ("phase2", gc.PROF_PHASE2))
+        else:
+            kinds = (("inc_a", gc.PROF_INC_A), ("inc_b", gc.PROF_INC_B), ("inc_c", gc.PROF_INC_C))
+        for name, kid in kinds:
+            ms, nl = gc.profile_read(kid)
+            kern[name] = dict(total_ms=ms / args.steps, launches=nl // args.steps,
+                              avg_us=1000.0 * ms / max(nl, 1))
+        gc.profile(False)
+        # algorithmic bytes per kernel over one colouring (per-unit figures:
+        # bytes every correct implementation of the kernel must move)
+        U = [u for _, u, _ in st.round_log]
+        E = [e for _, _, e in st.round_log]
+        C = [d[0] for d in st.detail]
+        D = [d[1] for d in st.detail]
+        DE = [d[2] for d in st.detail]
+        if args.engine == "plain":
+            # phase 1: neighbour id + its colour (8 B) per row entry; list entry,
+            # row_ptr pair and tentative write (16 B) per worklist vertex
+            algo = {"phase1": sum(8 * e + 16 * u for u, e in zip(U, E))}
+        else:
+            # inc_a: list entry, row_ptr pair, tentative read/write, old write
+            #        (24 B) per dirty vertex; neighbour id + its colour (8 B) per entry
+            # inc_b: list, row_ptr pair, split, tent, told, conf (28 B) per dirty
+            #        vertex; neighbour id + its tentative colour (8 B) per entry
+            # inc_c: list, tent, conf, row_ptr pair, colour and tent writes
+            #        (28 B) per committed vertex; neighbour id + its tentative
+            #        colour (8 B) per entry, each entry once per colouring
+            algo = {"inc_a": sum(24 * d + 8 * de for d, de in zip(D, DE)),
+                    "inc_b": sum(28 * d + 8 * de for d, de in zip(D, DE)),
+                    "inc_c": 28 * sum(C) + 8 * g.nnz}
+        dom = max(algo, key=lambda k: kern[k]["total_ms"])
+        launches = kern[dom]["launches"]
+        achieved = (algo[dom] / max(launches, 1)) / (kern[dom]["avg_us"] * 1e-6) / 1e9
+        traffic = load_traffic(args.workload, args.order, dom, launches)
+        roofline = {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_step": {k: int(v) for k, v in algo.items()},
+            "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
+        }
+        log("kernels: %s" % json.dumps(roofline["kernels"]))
+
+    # CPU oracle on the same workload, and serial greedy for the colour count
+    cpu = None
+    parity = None
+    greedy_colors = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.spec_sim(g.row_ptr, g.col_idx, key, threads=0)
+        dt = time.perf_counter() - t
+        parity = bool(np.array_equal(ref.colors, gpu_colors))
+        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "the full workload: every vertex and every round (%.1f s)" % dt}
+        t = time.perf_counter()
+        greedy_colors = int(oracle.greedy(g.row_ptr, g.col_idx, key).max())
+        log("oracle %.1fs parity=%s; serial greedy %d colours (%.1fs)"
+            % (dt, parity, greedy_colors, time.perf_counter() - t))
+
+    p = WORKLOADS[args.workload][1]
+    config = {"workload": "%s-%s" % (args.workload, args.order), "engine": args.engine,
+              "n": g.n, "nnz": g.nnz, "edges": g.edges}
+    config.update({k: v for k, v in p.items()})
+    res = {
+        "metric": "edges colored/sec + % HBM peak at R-MAT s24; colors vs serial greedy",
+        "value": round(edges_per_s, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": config,
+        "colors": int(st.num_colors),
+        "serial_greedy_colors": greedy_colors,
+        "rounds": int(st.rounds),
+        "edge_work_over_nnz": round(st.edge_work / max(g.nnz, 1), 3),
+        "parity_vs_oracle": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,152 @@
+/*
+ * gcolor -- speculative iterative distance-1 graph colouring on MI355X (gfx950).
+ *
+ * C ABI of libgcolor.so.  Method: Catalyurek, Feo, Gebremedhin, Halappanavar,
+ * Pothen, "Graph colouring algorithms for multi-core and massively
+ * multithreaded architectures", section "Iterative parallel coloring
+ * algorithm" (Algorithm 2), built on the serial first-fit of Algorithm 1.
+ *
+ * What is computed (the round-synchronous reading of Algorithm 2):
+ *   colour = 0 everywhere; U = all vertices
+ *   repeat until U is empty:
+ *     phase 1 (tentative colouring), for each v in U:
+ *       tent[v] = smallest c >= 1 not held by a neighbour, where the neighbours'
+ *       colours are those committed at the end of the previous round (vertices
+ *       still in U count as uncoloured);
+ *     phase 2 (conflict detection), for each v in U:
+ *       v is re-queued if a neighbour w in U has tent[w] == tent[v] and w
+ *       precedes v; otherwise v keeps tent[v] for good.
+ *   "w precedes v" means (priority[w], w) < (priority[v], v); with no priority
+ *   array the vertex index alone decides, as in the paper (the smaller index
+ *   keeps its colour).
+ * The result is a deterministic function of (graph, priority): it does not
+ * depend on launch shapes, thread timing or the order of the worklist.
+ *
+ * Graph format (all arrays in device memory, owned by the caller):
+ *   row_ptr  int32[n+1], row_ptr[0] == 0, non-decreasing, nnz = row_ptr[n] < 2^31;
+ *   col_idx  int32[nnz] (may be NULL when nnz == 0), neighbour ids in [0, n); the adjacency must be
+ *            symmetric (w in adj(v) iff v in adj(w)).  Without a priority array
+ *            every row must be sorted ascending.  Self-loops are ignored and
+ *            duplicate entries are harmless.
+ *   priority uint32[n] or NULL.
+ *   colors_out int32[n]: receives colours in [1, max degree + 1].
+ * Nothing is read or written outside these extents; the library never frees
+ * caller memory.
+ *
+ * Errors: every entry point returns 0 on success or a negative code
+ * (GCOLOR_E*); nothing aborts or throws across the ABI.  gcolor_strerror()
+ * names a code.  A HIP error raised by an earlier, unrelated call on the same
+ * device may surface here as GCOLOR_EHIP.
+ *
+ * Streams: all device work is enqueued on `stream` (0 = the null stream).  The
+ * colouring entry points read small counters back to the host to decide when
+ * the worklist is empty, so they return only after the colouring is complete.
+ */
+#ifndef GCOLOR_H
+#define GCOLOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gcolor_stream_t; /* same object as hipStream_t */
+
+enum {
+    GCOLOR_OK = 0,
+    GCOLOR_EINVAL = -1,     /* bad argument: negative n, NULL array, bad flags */
+    GCOLOR_ECSR = -2,       /* malformed CSR (reported only with GCOLOR_VALIDATE) */
+    GCOLOR_EWORKSPACE = -3, /* caller workspace smaller than gcolor_workspace_bytes */
+    GCOLOR_EHIP = -4,       /* a HIP runtime call failed */
+    GCOLOR_EROUNDS = -5,    /* round cap exceeded (never happens for valid input) */
+    GCOLOR_ENOTSUP = -6,    /* sizes beyond what this build supports */
+    GCOLOR_EINTERNAL = -7   /* an internal consistency check failed (a bug; report it) */
+};
+
+/* Flags for color_graph_ex. */
+enum {
+    GCOLOR_VALIDATE = 1u << 0, /* check the CSR on the device first (costs a pass) */
+    GCOLOR_STATS = 1u << 1,    /* fill *stats (rounds, colours, edge work) */
+    GCOLOR_PLAIN = 1u << 2     /* use the plain engine: every round rescans every worklist row
+                                  (same result as the default incremental engine) */
+};
+
+typedef struct gcolor_stats {
+    int32_t rounds;     /* number of rounds (a round = phase 1 + phase 2) */
+    int32_t num_colors; /* largest colour assigned */
+    int64_t edge_work;  /* sum over rounds of the degrees of the worklist */
+    int32_t status;     /* 0, or the code the call returned */
+    int32_t reserved;
+} gcolor_stats_t;
+
+/* Per-round record written to round_log (host memory) by color_graph_ex:
+ * round index (1-based), |U_k| (worklist size), E_k (sum of degrees over
+ * U_k), vertices committed in the round, and for the incremental engine the
+ * number of dirty vertices (tentative colour changed) and their degree sum. */
+typedef struct gcolor_round {
+    int64_t round;
+    int64_t worklist;
+    int64_t edge_work;
+    int64_t committed;
+    int64_t dirty;
+    int64_t dirty_edges;
+} gcolor_round_t;
+
+/* Bytes of device workspace color_graph_ex needs for a graph of this size. */
+size_t gcolor_workspace_bytes(int32_t n, int64_t nnz);
+
+/*
+ * Colour the graph.  Uses a workspace the library allocates on first use and
+ * keeps per device (grown when a larger graph arrives).  Returns 0 or a
+ * negative GCOLOR_E* code.
+ */
+int color_graph(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                const uint32_t* priority, int32_t* colors_out, gcolor_stream_t stream);
+
+/*
+ * As color_graph, with a caller-provided device workspace of ws_bytes bytes
+ * (>= gcolor_workspace_bytes(n, nnz); NULL selects the library's own), flags
+ * (GCOLOR_*), optional host pointers: stats (filled when GCOLOR_STATS is set)
+ * and round_log (capacity max_log records; the first min(rounds, max_log)
+ * rounds are written).
+ */
+int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                   const uint32_t* priority, int32_t* colors_out, void* workspace,
+                   size_t ws_bytes, uint32_t flags, gcolor_stats_t* stats,
+                   gcolor_round_t* round_log, int32_t max_log, gcolor_stream_t stream);
+
+/*
+ * Tuning (process-wide, applies to later calls): bin_limits[4] are the
+ * largest degrees of bins 0..3 (one lane, 4 lanes, 16 lanes and one
+ * wavefront per vertex); larger degrees take a workgroup per vertex.  Must be
+ * non-decreasing.  blocks_per_cu (1..64, 0 = keep) sizes the phase grids.
+ * NULL bin_limits keeps the current limits.  Results never depend on tuning.
+ */
+int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu);
+int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
+
+/*
+ * Kernel timing with HIP events recorded around every phase launch.
+ * gcolor_profile(1) enables it and clears the totals, gcolor_profile(0)
+ * disables it.  gcolor_profile_read(kernel, ...) returns the summed
+ * milliseconds and launch count of a kernel: 0 = plain phase 1 (tentative
+ * colouring), 1 = plain phase 2 (conflict detection and worklist
+ * compaction), 2 = incremental tentative colours of dirty vertices,
+ * 3 = incremental conflict counters, 4 = incremental commit and push.
+ */
+int gcolor_profile(int32_t enable);
+int gcolor_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Human-readable name of a return code. */
+const char* gcolor_strerror(int code);
+
+/* Library version string. */
+const char* gcolor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCOLOR_H */

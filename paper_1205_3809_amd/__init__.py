@@ -1,0 +1,30 @@
+"""MI355X-native speculative iterative graph colouring.
+
+The colouring itself runs in ``libgcolor.so`` (hand-written HIP for gfx950,
+C ABI in ``include/gcolor.h``); this package only marshals torch tensors into
+that ABI.  There is no CPU fallback: if the library is missing, importing the
+binding raises.
+"""
+from ._binding import (  # noqa: F401
+    GColorError,
+    Stats,
+    color_graph,
+    color_graph_ex,
+    library_path,
+    strerror,
+    version,
+    workspace_bytes,
+    FLAG_VALIDATE,
+    FLAG_STATS,
+    FLAG_PLAIN,
+    PROF_PHASE1,
+    PROF_PHASE2,
+    PROF_INC_A,
+    PROF_INC_B,
+    PROF_INC_C,
+    get_tuning,
+    profile,
+    profile_read,
+    raw_library,
+    set_tuning,
+)

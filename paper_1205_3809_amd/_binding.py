@@ -1,0 +1,228 @@
+"""ctypes binding of libgcolor.so (argument marshalling only).
+
+Every function here takes torch tensors that live on a HIP device, passes
+their raw device pointers and torch's current stream to the C ABI declared in
+``include/gcolor.h``, and turns negative return codes into ``GColorError``.
+No step of the colouring runs in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, NamedTuple, Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libgcolor.so")
+
+FLAG_VALIDATE = 1
+FLAG_STATS = 2
+FLAG_PLAIN = 4
+
+
+class GColorError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, strerror(code) if _lib else "?", code))
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("num_colors", ctypes.c_int32),
+                ("edge_work", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Round(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int64), ("worklist", ctypes.c_int64), ("edge_work", ctypes.c_int64),
+                ("committed", ctypes.c_int64), ("dirty", ctypes.c_int64), ("dirty_edges", ctypes.c_int64)]
+
+
+class Stats(NamedTuple):
+    rounds: int
+    num_colors: int
+    edge_work: int
+    round_log: List[Tuple[int, int, int]]  # (k, |U_k|, E_k)
+    detail: List[Tuple[int, int, int]]     # (committed, dirty, dirty degree sum) per round
+
+
+def library_path() -> str:
+    return _SO
+
+
+def _load():
+    if not os.path.exists(_SO):
+        raise ImportError(
+            "libgcolor.so is not built (%s); run `python -m paper_1205_3809_amd.build` "
+            "or __graft_entry__.build()" % _SO)
+    lib = ctypes.CDLL(_SO)
+    vp = ctypes.c_void_p
+    lib.gcolor_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.gcolor_workspace_bytes.restype = ctypes.c_size_t
+    lib.color_graph.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
+    lib.color_graph.restype = ctypes.c_int
+    lib.color_graph_ex.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_uint32,
+                                   ctypes.POINTER(_Stats), ctypes.POINTER(_Round), ctypes.c_int32, vp]
+    lib.color_graph_ex.restype = ctypes.c_int
+    lib.gcolor_strerror.argtypes = [ctypes.c_int]
+    lib.gcolor_strerror.restype = ctypes.c_char_p
+    lib.gcolor_version.argtypes = []
+    lib.gcolor_version.restype = ctypes.c_char_p
+    lib.gcolor_set_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.gcolor_set_tuning.restype = ctypes.c_int
+    lib.gcolor_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.gcolor_get_tuning.restype = ctypes.c_int
+    lib.gcolor_profile.argtypes = [ctypes.c_int32]
+    lib.gcolor_profile.restype = ctypes.c_int
+    lib.gcolor_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.gcolor_profile_read.restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def strerror(code: int) -> str:
+    return _lib.gcolor_strerror(int(code)).decode()
+
+
+def version() -> str:
+    return _lib.gcolor_version().decode()
+
+
+def workspace_bytes(n: int, nnz: int) -> int:
+    return int(_lib.gcolor_workspace_bytes(int(n), int(nnz)))
+
+
+def _dev_ptr(t: Optional[torch.Tensor], name: str, dtypes, n: Optional[int] = None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be on a HIP device (got %s)" % (name, t.device))
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_I32 = (torch.int32,)
+_KEY = (torch.int32, torch.uint32) if hasattr(torch, "uint32") else (torch.int32,)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def color_graph_ex(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional[torch.Tensor] = None,
+                   colors_out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                   flags: int = 0, stats: bool = False, max_log: int = 0, stream=None):
+    """Colour a symmetric CSR graph on its device.  Returns (colors, Stats or None).
+
+    priority (int32/uint32, bit pattern taken as uint32) sets the precedence
+    (priority, id); None means the vertex index alone (rows must be sorted).
+    """
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must have n+1 entries")
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    pr = _dev_ptr(priority, "priority", _KEY, n)
+    if colors_out is None:
+        colors_out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    co = _dev_ptr(colors_out, "colors_out", _I32, n)
+    ws = None
+    ws_bytes = 0
+    if workspace is not None:
+        ws = _dev_ptr(workspace, "workspace", (torch.uint8, torch.int8, torch.int32, torch.int64))
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = _Stats()
+    want = stats or max_log > 0
+    if want:
+        flags |= FLAG_STATS
+    logbuf = (_Round * max(max_log, 1))() if max_log > 0 else None
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.color_graph_ex(n, rp, ci, pr, co, ws, ws_bytes, flags,
+                                 ctypes.byref(st) if want else None,
+                                 logbuf if logbuf is not None else None, max_log, _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "color_graph_ex")
+    if not want:
+        return colors_out, None
+    log = []
+    detail = []
+    if logbuf is not None:
+        for i in range(min(st.rounds, max_log)):
+            log.append((int(logbuf[i].round), int(logbuf[i].worklist), int(logbuf[i].edge_work)))
+            detail.append((int(logbuf[i].committed), int(logbuf[i].dirty), int(logbuf[i].dirty_edges)))
+    return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), log, detail)
+
+
+def color_graph(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional[torch.Tensor] = None,
+                colors_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Colour with the library's own cached workspace; returns colors_out."""
+    n = row_ptr.numel() - 1
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    pr = _dev_ptr(priority, "priority", _KEY, n)
+    if colors_out is None:
+        colors_out = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    co = _dev_ptr(colors_out, "colors_out", _I32, n)
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.color_graph(n, rp, ci, pr, co, _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "color_graph")
+    return colors_out
+
+
+def set_tuning(bin_limits=None, blocks_per_cu: int = 0) -> None:
+    """Degree-bin limits (4 non-decreasing ints) and blocks per CU of the
+    phase grids; affects speed only, never the colouring."""
+    arr = None
+    if bin_limits is not None:
+        if len(bin_limits) != 4:
+            raise ValueError("bin_limits needs 4 entries")
+        arr = (ctypes.c_int32 * 4)(*[int(x) for x in bin_limits])
+    rc = _lib.gcolor_set_tuning(arr, int(blocks_per_cu))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_set_tuning")
+
+
+def get_tuning():
+    arr = (ctypes.c_int32 * 4)()
+    bpc = ctypes.c_int32()
+    _lib.gcolor_get_tuning(arr, ctypes.byref(bpc))
+    return list(arr), int(bpc.value)
+
+
+PROF_PHASE1 = 0   # plain engine: tentative colouring
+PROF_PHASE2 = 1   # plain engine: conflict detection + compaction
+PROF_INC_A = 2    # incremental: tentative colours of dirty vertices
+PROF_INC_B = 3    # incremental: conflict counters, candidates
+PROF_INC_C = 4    # incremental: commit + push
+
+
+def profile(enable: bool) -> None:
+    """Turn per-launch HIP-event timing of the phase kernels on (totals cleared) or off."""
+    _lib.gcolor_profile(1 if enable else 0)
+
+
+def profile_read(kernel: int):
+    """(total milliseconds, launches) recorded for kernel PROF_PHASE1 / PROF_PHASE2."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    rc = _lib.gcolor_profile_read(int(kernel), ctypes.byref(ms), ctypes.byref(n))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def raw_library():
+    """The loaded ctypes library (for ABI-level tests)."""
+    return _lib

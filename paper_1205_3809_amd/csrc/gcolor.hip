@@ -1,0 +1,1420 @@
+// Speculative iterative distance-1 colouring for gfx950 (MI355X).
+//
+// Method: the iterative parallel colouring of Catalyurek et al. (Algorithm 2:
+// rounds of tentative first-fit colouring of a worklist, then conflict
+// detection that re-queues the later vertex of each conflicting edge), run
+// round-synchronously: phase 1 reads only colours committed in earlier rounds,
+// so the result is a pure function of (graph, priority).
+//
+// Two engines compute that same function:
+//
+//  * plain: each round rescans every worklist row in both phases, exactly as
+//    the two parallel loops of Algorithm 2 do.  Kernels k_phase1 (tentative
+//    first-fit against committed neighbour colours) and k_phase2 (conflict
+//    detection, commit of winners, compaction of losers into the next
+//    worklist).
+//
+//  * incremental (default): keeps per uncoloured vertex its tentative colour
+//    and conf[v] = number of preceding worklist neighbours holding the same
+//    tentative colour; a vertex loses a round exactly when conf[v] > 0.  Only
+//    events change this state.  A commit of colour t marks "dirty" each
+//    uncoloured neighbour whose tentative colour is t (its tentative colour
+//    must move); a dirty vertex re-takes first-fit over its row and has its
+//    counter recounted, and its later neighbours adjust their counters by +-1.
+//    Tentative colours of other vertices cannot change (their forbidden sets
+//    only grew by colours they do not hold), so rounds are the plain engine's,
+//    vertex for vertex.  Kernels per round: k_inc_a (first-fit of dirty
+//    vertices), k_inc_b (counter recount and updates, candidate list), k_inc_c
+//    (commit of candidates whose counter is 0, dirty marks to neighbours).
+//    A committed vertex's tentative colour is set to 0, so one gather of a
+//    neighbour's tentative colour tells both "uncoloured" and "same colour".
+//
+// Degree bins (the vertex-to-lane mapping of every row-scanning kernel):
+//   bin 0: one lane per vertex         bin 1: 4 lanes per vertex
+//   bin 2: 16 lanes per vertex         bin 3: one wavefront (64 lanes)
+//   bin 4: one workgroup (256 lanes)
+// Lanes of a group stride over the row (coalesced CSR reads); first-fit builds
+// a 64-colour window bitset per lane, ORs it across the group with shuffles
+// (LDS across the waves of bin 4) and takes ctz(~mask); a full window moves
+// on to the next 64 colours.
+//
+// List appends go through a per-workgroup LDS stage (wave ballot + LDS
+// atomic), flushed to the global lists with one global atomic per bin; global
+// atomics on a shared counter are ~300x slower than LDS ones on this chip.
+//
+// Each kernel is one launch of a fixed grid; blocks walk a chunk space that
+// concatenates the bins (heaviest first), so hubs spread across the chip.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "gcolor.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kBins = 5;
+constexpr int kSets = 4;          // list sets: 0,1 = worklist/dirty ping-pong, 2,3 = candidates
+constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
+constexpr int kLogW = 4;          // int64 words per logged round
+
+// Vertices covered by one block-sized chunk of each bin.
+__host__ __device__ constexpr int chunk_vertices(int b) {
+    return b == 0 ? 256 : b == 1 ? 64 : b == 2 ? 16 : b == 3 ? 4 : 1;
+}
+
+// LDS stage capacity per bin and offsets into the stage array.
+__host__ __device__ constexpr int stage_cap(int b) {
+    return b == 0 ? 1024 : b == 1 ? 512 : b == 2 ? 256 : b == 3 ? 128 : 64;
+}
+__host__ __device__ constexpr int stage_off(int b) {
+    return b == 0 ? 0 : b == 1 ? 1024 : b == 2 ? 1536 : b == 3 ? 1792 : 1920;
+}
+constexpr int kStageTotal = 1984;
+
+struct BinCfg {
+    int dmax[4];  // bin b (b < 4) holds degrees <= dmax[b]; bin 4 the rest
+};
+
+struct Ctl {
+    int32_t cnt[kSets][8];  // [list set][bin] list lengths
+    int32_t rounds;         // last round that committed a vertex
+    int32_t err;            // validation error bits
+    int32_t maxcolor;
+    int32_t pad0;
+    unsigned long long committed;  // vertices committed so far
+    int32_t pad[10];
+};
+static_assert(sizeof(Ctl) == 192, "ctl layout");
+
+struct Args {
+    int n;
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ colp;  // original col_idx, or the reordered copy
+    int* __restrict__ split;       // entries at the front of each row that precede the vertex
+    int* __restrict__ color;       // the caller's colors_out: 0 until committed
+    int* __restrict__ tent;        // tentative colour (incremental: 0 once committed)
+    int* __restrict__ told;        // (incremental) tentative colour before this round's change
+    int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
+    int* __restrict__ stamp;       // (incremental) round of last dirty mark
+    int* __restrict__ cflag;       // (incremental) round of last candidate mark
+    int* __restrict__ lists;       // [kSets][kBins][n]
+    Ctl* ctl;
+    long long* __restrict__ log;   // [kMaxLog][kLogW]
+    BinCfg cfg;
+};
+
+struct Stage {
+    int cnt[kBins];
+    int base[kBins];
+    int q[kStageTotal];
+};
+
+__device__ __forceinline__ int bin_of(int deg, const BinCfg& c) {
+    return deg <= c.dmax[0] ? 0 : deg <= c.dmax[1] ? 1 : deg <= c.dmax[2] ? 2 : deg <= c.dmax[3] ? 3 : 4;
+}
+
+__device__ __forceinline__ int* list_ptr(const Args& a, int set, int b) {
+    return a.lists + ((size_t)(set * kBins + b)) * (size_t)a.n;
+}
+
+template <int GS>
+__device__ __forceinline__ uint64_t group_or(uint64_t m) {
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) m |= __shfl_xor(m, o, GS);
+    return m;
+}
+
+template <int GS>
+__device__ __forceinline__ int group_sum(int x) {
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, GS);
+    return x;
+}
+
+// Bits of `ballot` belonging to this lane's group of GS lanes.
+template <int GS>
+__device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int lane) {
+    if constexpr (GS == 64) {
+        return ballot;
+    } else {
+        const int gbase = lane & ~(GS - 1);
+        return (ballot >> gbase) & ((1ull << GS) - 1ull);
+    }
+}
+
+__device__ __forceinline__ void stage_init(Stage* st) {
+    if (threadIdx.x < kBins) st->cnt[threadIdx.x] = 0;
+    __syncthreads();
+}
+
+// Staged append of the active lanes with pred set into bin b of list set
+// `set`: one LDS atomic per wavefront and bin; entries beyond the stage
+// capacity go straight to the global list.  Safe in divergent code: every
+// active lane must call it, the leader of each ballot is an active lane.
+__device__ __forceinline__ void stage_append(const Args& a, Stage* st, bool pred, int v, int deg, int set) {
+    const uint64_t any = __ballot(pred);
+    if (any == 0) return;
+    const int b = pred ? bin_of(deg, a.cfg) : -1;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 0; k < kBins; ++k) {
+        const uint64_t m = __ballot(b == k);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&st->cnt[k], __popcll(m));
+        base = __shfl(base, leader);
+        if (b == k) {
+            const int slot = base + __popcll(m & __lanemask_lt());
+            if (slot < stage_cap(k)) {
+                st->q[stage_off(k) + slot] = v;
+            } else {
+                const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
+                list_ptr(a, set, k)[g] = v;
+            }
+        }
+    }
+}
+
+// Staged append where the degree must still be looked up.
+__device__ __forceinline__ void stage_append_lookup(const Args& a, Stage* st, bool pred, int v, int set) {
+    if (__ballot(pred) == 0) return;
+    const int deg = pred ? a.row_ptr[v + 1] - a.row_ptr[v] : 0;
+    stage_append(a, st, pred, v, deg, set);
+}
+
+// Move the staged entries to the global lists (block-uniform call).
+__device__ __forceinline__ void stage_flush(const Args& a, Stage* st, int set) {
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+        const int b = threadIdx.x;
+        const int c = min(st->cnt[b], stage_cap(b));
+        st->base[b] = c ? atomicAdd(&a.ctl->cnt[set][b], c) : 0;
+        st->cnt[b] = c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        int* dst = list_ptr(a, set, b) + st->base[b];
+        for (int i = threadIdx.x; i < st->cnt[b]; i += blockDim.x) dst[i] = st->q[stage_off(b) + i];
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins) st->cnt[threadIdx.x] = 0;
+    __syncthreads();
+}
+
+// Flush when any bin is at least half full (block-uniform call).
+__device__ __forceinline__ void stage_maybe_flush(const Args& a, Stage* st, int set) {
+    __syncthreads();
+    bool full = false;
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) full |= st->cnt[b] * 2 >= stage_cap(b);
+    if (full) stage_flush(a, st, set);
+}
+
+struct ChunkMap {
+    int cnt[kBins];
+    int start[kBins];  // chunk-space start of each bin; bins ordered 4,3,2,1,0
+    int total;
+};
+
+__device__ __forceinline__ ChunkMap make_map(const Ctl* ctl, int set) {
+    ChunkMap m;
+    int tot = 0;
+    for (int b = kBins - 1; b >= 0; --b) {
+        m.cnt[b] = ctl->cnt[set][b];
+        m.start[b] = tot;
+        tot += (m.cnt[b] + chunk_vertices(b) - 1) / chunk_vertices(b);
+    }
+    m.total = tot;
+    return m;
+}
+
+__device__ __forceinline__ int chunk_bin(const ChunkMap& m, int c) {
+    int b = kBins - 1;
+    while (b > 0 && c >= m.start[b - 1]) --b;
+    return b;
+}
+
+// Smallest colour >= base not held by a committed neighbour in the row
+// [s, e).  Uncommitted neighbours hold 0, which no window contains.
+template <int GS>
+__device__ __forceinline__ int first_fit_group(int s, int e, int lig, int base, const int* __restrict__ colp,
+                                               const int* __restrict__ color) {
+    for (;;) {
+        uint64_t m = 0;
+        int p = s + lig;
+        for (; p + 3 * GS < e; p += 4 * GS) {
+            const int w0 = colp[p], w1 = colp[p + GS], w2 = colp[p + 2 * GS], w3 = colp[p + 3 * GS];
+            const unsigned c0 = (unsigned)(color[w0] - base);
+            const unsigned c1 = (unsigned)(color[w1] - base);
+            const unsigned c2 = (unsigned)(color[w2] - base);
+            const unsigned c3 = (unsigned)(color[w3] - base);
+            if (c0 < 64u) m |= 1ull << c0;
+            if (c1 < 64u) m |= 1ull << c1;
+            if (c2 < 64u) m |= 1ull << c2;
+            if (c3 < 64u) m |= 1ull << c3;
+        }
+        for (; p < e; p += GS) {
+            const unsigned c = (unsigned)(color[colp[p]] - base);
+            if (c < 64u) m |= 1ull << c;
+        }
+        m = group_or<GS>(m);
+        if (~m) return base + __builtin_ctzll(~m);
+        base += 64;
+    }
+}
+
+// Block-wide version for bin 4 (red: 4 words of LDS).
+__device__ __forceinline__ int first_fit_block(int s, int e, int base, const int* __restrict__ colp,
+                                               const int* __restrict__ color, uint64_t* red) {
+    const int wid = threadIdx.x / kWave;
+    for (;;) {
+        uint64_t m = 0;
+        for (int p = s + (int)threadIdx.x; p < e; p += kBlock) {
+            const unsigned c = (unsigned)(color[colp[p]] - base);
+            if (c < 64u) m |= 1ull << c;
+        }
+        m = group_or<kWave>(m);
+        if (__lane_id() == 0) red[wid] = m;
+        __syncthreads();
+        const uint64_t all = red[0] | red[1] | red[2] | red[3];
+        __syncthreads();
+        if (~all) return base + __builtin_ctzll(~all);
+        base += 64;
+    }
+}
+
+// Walk the chunk space of list set SET: each chunk runs BODY_GS(GS, list,
+// count, local chunk index) for the group bins or BODY_BLOCK(vertex) for
+// the workgroup bin, then AFTER() (block-uniform).
+#define GC_FOR_CHUNKS(A, SET, BODY_GS, BODY_BLOCK, AFTER)                              \
+    {                                                                                  \
+        const ChunkMap m_ = make_map((A).ctl, (SET));                                  \
+        for (int c_ = blockIdx.x; c_ < m_.total; c_ += gridDim.x) {                     \
+            const int b_ = chunk_bin(m_, c_);                                          \
+            const int local_ = c_ - m_.start[b_];                                      \
+            const int* list_ = list_ptr((A), (SET), b_);                               \
+            const int cnt_ = m_.cnt[b_];                                               \
+            switch (b_) {                                                              \
+                case 0: BODY_GS(1, list_, cnt_, local_); break;                        \
+                case 1: BODY_GS(4, list_, cnt_, local_); break;                        \
+                case 2: BODY_GS(16, list_, cnt_, local_); break;                       \
+                case 3: BODY_GS(64, list_, cnt_, local_); break;                       \
+                default: BODY_BLOCK(list_[local_]); break;                             \
+            }                                                                          \
+            AFTER();                                                                   \
+        }                                                                              \
+    }
+
+#define GC_NOTHING() \
+    do {             \
+    } while (0)
+
+__device__ __forceinline__ void block_add_log(long long x, long long* slot) {
+    __shared__ long long part[kBlock / kWave];
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    __syncthreads();
+    if (__lane_id() == 0) part[threadIdx.x / kWave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd((unsigned long long*)slot, (unsigned long long)t);
+    }
+}
+
+// ===========================================================================
+// Plain engine (rounds k = 0, 1, ... on worklist sets k & 1)
+// ===========================================================================
+
+template <int GS>
+__device__ __forceinline__ void phase1_chunk(const Args& a, const int* list, int cnt, int local) {
+    constexpr int CV = kBlock / GS;
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    if (idx < cnt) {
+        const int v = list[idx];
+        const int t = first_fit_group<GS>(a.row_ptr[v], a.row_ptr[v + 1], lig, 1, a.colp, a.color);
+        if (lig == 0) a.tent[v] = t;
+    }
+}
+
+// Phase 1 of round k over worklist set `side`: tentative first-fit.
+__global__ __launch_bounds__(kBlock) void k_phase1(Args a, int side, int k) {
+    __shared__ uint64_t red[kBlock / kWave];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int usize = 0;
+        for (int b = 0; b < kBins; ++b) usize += a.ctl->cnt[side][b];
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[side ^ 1][b] = 0;
+        if (usize > 0) {
+            a.ctl->rounds = k + 1;
+            if (k < kMaxLog) {
+                a.log[kLogW * k] = usize;
+                a.log[kLogW * k + 1] = 0;
+            }
+        }
+    }
+#define P1_GS(GS, L, C, LOC) phase1_chunk<GS>(a, L, C, LOC)
+#define P1_BLOCK(V)                                                                                \
+    {                                                                                              \
+        const int v_ = (V);                                                                        \
+        const int t_ = first_fit_block(a.row_ptr[v_], a.row_ptr[v_ + 1], 1, a.colp, a.color, red); \
+        if (threadIdx.x == 0) a.tent[v_] = t_;                                                     \
+    }
+    GC_FOR_CHUNKS(a, side, P1_GS, P1_BLOCK, GC_NOTHING)
+#undef P1_GS
+#undef P1_BLOCK
+}
+
+// Does some entry of the preceding prefix [s, lim) hold tentative colour t?
+// Neighbours committed in earlier rounds cannot: phase 1 avoided their colours.
+template <int GS>
+__device__ __forceinline__ bool loses_group(int s, int lim, int t, int lig, int lane,
+                                            const int* __restrict__ colp, const int* __restrict__ tent) {
+    for (int p0 = s; p0 < lim; p0 += GS) {
+        const int p = p0 + lig;
+        const bool hit = (p < lim) && (tent[colp[p]] == t);
+        if constexpr (GS == 1) {
+            if (hit) return true;
+        } else {
+            if (group_bits<GS>(__ballot(hit), lane)) return true;
+        }
+    }
+    return false;
+}
+
+template <int GS>
+__device__ __forceinline__ void phase2_chunk(const Args& a, Stage* st, const int* list, int cnt, int local,
+                                             int nside, long long* ework) {
+    constexpr int CV = kBlock / GS;
+    const int lane = __lane_id();
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    bool lose = false;
+    int v = 0, deg = 0;
+    if (idx < cnt) {
+        v = list[idx];
+        const int s = a.row_ptr[v];
+        deg = a.row_ptr[v + 1] - s;
+        if (lig == 0) *ework += deg;
+        const int t = a.tent[v];
+        lose = loses_group<GS>(s, s + a.split[v], t, lig, lane, a.colp, a.tent);
+        if (!lose && lig == 0) a.color[v] = t;
+    }
+    stage_append(a, st, lose && lig == 0, v, deg, nside);
+}
+
+__device__ __forceinline__ void phase2_block(const Args& a, Stage* st, int v, int nside, long long* ework) {
+    const int s = a.row_ptr[v];
+    const int lim = s + a.split[v];
+    const int t = a.tent[v];
+    bool lose = false;
+    for (int p0 = s; p0 < lim; p0 += kBlock) {
+        const int p = p0 + (int)threadIdx.x;
+        const int hit = (p < lim) && (a.tent[a.colp[p]] == t);
+        if (__syncthreads_or(hit)) {
+            lose = true;
+            break;
+        }
+    }
+    const int deg = a.row_ptr[v + 1] - s;
+    if (threadIdx.x == 0) {
+        *ework += deg;
+        if (!lose) a.color[v] = t;
+    }
+    if (threadIdx.x < kWave) stage_append(a, st, lose && threadIdx.x == 0, v, deg, nside);
+}
+
+// Phase 2 of round k: conflict detection, commit, compaction into side^1.
+__global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
+    __shared__ Stage st;
+    stage_init(&st);
+    const int nside = side ^ 1;
+    long long ework = 0;
+#define P2_GS(GS, L, C, LOC) phase2_chunk<GS>(a, &st, L, C, LOC, nside, &ework)
+#define P2_BLOCK(V) phase2_block(a, &st, (V), nside, &ework)
+#define P2_AFTER() stage_maybe_flush(a, &st, nside)
+    GC_FOR_CHUNKS(a, side, P2_GS, P2_BLOCK, P2_AFTER)
+#undef P2_GS
+#undef P2_BLOCK
+#undef P2_AFTER
+    stage_flush(a, &st, nside);
+    if (k < kMaxLog) block_add_log(ework, &a.log[kLogW * k + 1]);
+}
+
+// ===========================================================================
+// Incremental engine (rounds k = 1, 2, ...; round 1 needs only k_inc_c)
+// ===========================================================================
+
+__host__ __device__ inline int dset(int k) { return k & 1; }
+__host__ __device__ inline int cset(int k) { return 2 + (k & 1); }
+
+// Round-1 state: every tentative colour is 1, so conf[v] is the number of
+// preceding neighbours; vertices with none are the round-1 candidates.
+// Natural order (rows sorted): split[v] = lower_bound(row, v) - row start.
+__global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
+    __shared__ Stage st;
+    stage_init(&st);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[dset(2)][b] = 0;  // held the set-up bins
+        for (int i = 0; i < kLogW; ++i) a.log[i] = 0;
+    }
+    const int stride = gridDim.x * kBlock;
+    for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
+        const int v = base + (int)threadIdx.x;
+        const bool ok = v < a.n;
+        int deg = 0, sp = -1;
+        if (ok) {
+            const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+            deg = e - s;
+            if (natural) {
+                int lo = s, hi = e;
+                while (lo < hi) {
+                    const int mid = lo + ((hi - lo) >> 1);
+                    if (a.colp[mid] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                sp = lo - s;
+                a.split[v] = sp;
+            } else {
+                sp = a.split[v];
+            }
+            a.color[v] = 0;
+            a.tent[v] = 1;
+            a.told[v] = 0;
+            a.conf[v] = sp;
+            a.stamp[v] = 0;
+            a.cflag[v] = 0;
+        }
+        stage_append(a, &st, ok && sp == 0, v, deg, cset(1));
+        stage_maybe_flush(a, &st, cset(1));
+    }
+    stage_flush(a, &st, cset(1));
+}
+
+// Round k: new tentative colours of the dirty vertices: first-fit over the
+// committed colours of the row.
+template <int GS>
+__device__ __forceinline__ void inc_a_chunk(const Args& a, const int* list, int cnt, int local) {
+    constexpr int CV = kBlock / GS;
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    if (idx < cnt) {
+        const int u = list[idx];
+        const int t = first_fit_group<GS>(a.row_ptr[u], a.row_ptr[u + 1], lig, 1, a.colp, a.color);
+        if (lig == 0) {
+            a.told[u] = a.tent[u];
+            a.tent[u] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
+    __shared__ uint64_t red[kBlock / kWave];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int b = 0; b < 8; ++b) {
+            a.ctl->cnt[dset(k + 1)][b] = 0;
+            a.ctl->cnt[cset(k)][b] = 0;
+        }
+        if (k - 1 < kMaxLog) {
+            long long nd = 0;
+            for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dset(k)][b];
+            a.log[kLogW * (k - 1) + 0] = 0;
+            a.log[kLogW * (k - 1) + 1] = 0;
+            a.log[kLogW * (k - 1) + 2] = nd;
+            a.log[kLogW * (k - 1) + 3] = 0;
+        }
+    }
+#define A_GS(GS, L, C, LOC) inc_a_chunk<GS>(a, L, C, LOC)
+#define A_BLOCK(V)                                                                                 \
+    {                                                                                              \
+        const int u_ = (V);                                                                        \
+        const int t_ = first_fit_block(a.row_ptr[u_], a.row_ptr[u_ + 1], 1, a.colp, a.color, red); \
+        if (threadIdx.x == 0) {                                                                    \
+            a.told[u_] = a.tent[u_];                                                               \
+            a.tent[u_] = t_;                                                                       \
+        }                                                                                          \
+    }
+    GC_FOR_CHUNKS(a, dset(k), A_GS, A_BLOCK, GC_NOTHING)
+#undef A_GS
+#undef A_BLOCK
+}
+
+// One row entry of a dirty vertex w (tentative colour changed old -> now):
+// the preceding part recounts w's own counter, the rest adjusts the counter
+// of each later neighbour x whose tentative colour equals old or now.  x's
+// own recount covers the case where x is dirty too; committed x hold
+// tentative colour 0 and never match.  Returns true when x's counter just
+// dropped to 0 and x was not yet a candidate this round.
+__device__ __forceinline__ bool inc_b_entry(const Args& a, int k, int w, int p, int lim, int now, int old,
+                                            int* cnt, int* xout) {
+    const int x = a.colp[p];
+    const int tx = a.tent[x];
+    *xout = x;
+    if (p < lim) {
+        *cnt += (tx == now);
+        return false;
+    }
+    if (x == w || (tx != now && tx != old)) return false;
+    if (a.stamp[x] == k) return false;
+    if (tx == now) {
+        atomicAdd(&a.conf[x], 1);
+        return false;
+    }
+    if (atomicSub(&a.conf[x], 1) != 1) return false;
+    return atomicExch(&a.cflag[x], k) != k;
+}
+
+template <int GS>
+__device__ __forceinline__ void inc_b_chunk(const Args& a, Stage* st, int k, const int* list, int cnt, int local,
+                                            long long* dedges) {
+    constexpr int CV = kBlock / GS;
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    const int cs = cset(k);
+    if (idx < cnt) {
+        const int w = list[idx];
+        const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
+        const int lim = s + a.split[w];
+        const int now = a.tent[w], old = a.told[w];
+        if (lig == 0) *dedges += e - s;
+        int c = 0;
+        for (int p = s + lig; p < e; p += GS) {
+            int x;
+            const bool cand = inc_b_entry(a, k, w, p, lim, now, old, &c, &x);
+            stage_append_lookup(a, st, cand, x, cs);
+        }
+        c = group_sum<GS>(c);
+        bool cand = false;
+        if (lig == 0) {
+            a.conf[w] = c;
+            cand = (c == 0) && (atomicExch(&a.cflag[w], k) != k);
+        }
+        stage_append(a, st, cand, w, e - s, cs);
+    }
+}
+
+__device__ __forceinline__ void inc_b_block(const Args& a, Stage* st, int k, int w, int* sh, long long* dedges) {
+    const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
+    const int lim = s + a.split[w];
+    const int now = a.tent[w], old = a.told[w];
+    const int cs = cset(k);
+    if (threadIdx.x == 0) *dedges += e - s;
+    int c = 0;
+    for (int p = s + (int)threadIdx.x; p < e; p += kBlock) {
+        int x;
+        const bool cand = inc_b_entry(a, k, w, p, lim, now, old, &c, &x);
+        stage_append_lookup(a, st, cand, x, cs);
+    }
+    c = group_sum<kWave>(c);
+    if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
+    __syncthreads();
+    const int tot = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    bool cand = false;
+    if (threadIdx.x == 0) {
+        a.conf[w] = tot;
+        cand = (tot == 0) && (atomicExch(&a.cflag[w], k) != k);
+    }
+    if (threadIdx.x < kWave) stage_append(a, st, cand, w, e - s, cs);
+}
+
+__global__ __launch_bounds__(kBlock) void k_inc_b(Args a, int k) {
+    __shared__ int sh[kBlock / kWave];
+    __shared__ Stage st;
+    stage_init(&st);
+    long long dedges = 0;
+    const int cs = cset(k);
+#define B_GS(GS, L, C, LOC) inc_b_chunk<GS>(a, &st, k, L, C, LOC, &dedges)
+#define B_BLOCK(V) inc_b_block(a, &st, k, (V), sh, &dedges)
+#define B_AFTER() stage_maybe_flush(a, &st, cs)
+    GC_FOR_CHUNKS(a, dset(k), B_GS, B_BLOCK, B_AFTER)
+#undef B_GS
+#undef B_BLOCK
+#undef B_AFTER
+    stage_flush(a, &st, cs);
+    if (k - 1 < kMaxLog) block_add_log(dedges, &a.log[kLogW * (k - 1) + 3]);
+}
+
+// Dirty mark from a committed vertex v (colour t) to one row entry u: u is
+// uncoloured with tentative colour t, so its tentative colour must move in
+// round k+1.  Returns true for the first mark of u.
+__device__ __forceinline__ bool inc_c_entry(const Args& a, int k, int v, int u, int t) {
+    if (u == v || a.tent[u] != t) return false;  // committed u hold 0 and never match
+    if (a.stamp[u] == k + 1) return false;
+    return atomicExch(&a.stamp[u], k + 1) != k + 1;
+}
+
+template <int GS>
+__device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* st, int k, const int* list, int cnt, int local,
+                                            long long* ncom, long long* ndeg) {
+    constexpr int CV = kBlock / GS;
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    const int ds = dset(k + 1);
+    if (idx < cnt) {
+        const int v = list[idx];
+        const int t = a.tent[v];
+        if (a.conf[v] == 0 && t != 0) {
+            const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+            for (int p = s + lig; p < e; p += GS) {
+                const int u = a.colp[p];
+                const bool dirty = inc_c_entry(a, k, v, u, t);
+                stage_append_lookup(a, st, dirty, u, ds);
+            }
+            if (lig == 0) {
+                a.color[v] = t;
+                a.tent[v] = 0;
+                *ncom += 1;
+                *ndeg += e - s;
+                a.ctl->rounds = k;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void inc_c_block(const Args& a, Stage* st, int k, int v, long long* ncom,
+                                            long long* ndeg) {
+    const int t = a.tent[v];
+    if (a.conf[v] != 0 || t == 0) return;  // block-uniform: nothing writes them in this kernel for v
+    const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+    const int ds = dset(k + 1);
+    for (int p = s + (int)threadIdx.x; p < e; p += kBlock) {
+        const int u = a.colp[p];
+        const bool dirty = inc_c_entry(a, k, v, u, t);
+        stage_append_lookup(a, st, dirty, u, ds);
+    }
+    __syncthreads();  // every thread has read tent[v] before it is cleared
+    if (threadIdx.x == 0) {
+        a.color[v] = t;
+        a.tent[v] = 0;
+        *ncom += 1;
+        *ndeg += e - s;
+        a.ctl->rounds = k;
+    }
+}
+
+// Round k: commit every candidate whose counter is 0, mark its dirty
+// neighbours for round k+1.
+__global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
+    __shared__ Stage st;
+    stage_init(&st);
+    long long ncom = 0, ndeg = 0;
+    const int ds = dset(k + 1);
+#define C_GS(GS, L, C, LOC) inc_c_chunk<GS>(a, &st, k, L, C, LOC, &ncom, &ndeg)
+#define C_BLOCK(V) inc_c_block(a, &st, k, (V), &ncom, &ndeg)
+#define C_AFTER() stage_maybe_flush(a, &st, ds)
+    GC_FOR_CHUNKS(a, cset(k), C_GS, C_BLOCK, C_AFTER)
+#undef C_GS
+#undef C_BLOCK
+#undef C_AFTER
+    stage_flush(a, &st, ds);
+    block_add_log(ncom, (long long*)&a.ctl->committed);
+    if (k - 1 < kMaxLog) {
+        block_add_log(ncom, &a.log[kLogW * (k - 1)]);
+        block_add_log(ndeg, &a.log[kLogW * (k - 1) + 1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up: clear colours, split points, initial binned worklist.
+// ---------------------------------------------------------------------------
+
+// Natural order (no priority): rows are sorted, so the neighbours preceding v
+// are the prefix below v; split[v] = lower_bound(row, v) - row start.
+__global__ __launch_bounds__(kBlock) void k_setup_natural(Args a, int* split) {
+    __shared__ Stage st;
+    stage_init(&st);
+    const int stride = gridDim.x * kBlock;
+    for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
+        const int v = base + (int)threadIdx.x;
+        const bool ok = v < a.n;
+        int deg = 0;
+        if (ok) {
+            const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+            deg = e - s;
+            int lo = s, hi = e;
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (a.colp[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            split[v] = lo - s;
+            a.color[v] = 0;
+        }
+        stage_append(a, &st, ok, v, deg, 0);
+        stage_maybe_flush(a, &st, 0);
+    }
+    stage_flush(a, &st, 0);
+}
+
+// Priority order, step 1: clear colours and bin every vertex.
+__global__ __launch_bounds__(kBlock) void k_setup_bins(Args a) {
+    __shared__ Stage st;
+    stage_init(&st);
+    const int stride = gridDim.x * kBlock;
+    for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
+        const int v = base + (int)threadIdx.x;
+        const bool ok = v < a.n;
+        int deg = 0;
+        if (ok) {
+            deg = a.row_ptr[v + 1] - a.row_ptr[v];
+            a.color[v] = 0;
+        }
+        stage_append(a, &st, ok, v, deg, 0);
+        stage_maybe_flush(a, &st, 0);
+    }
+    stage_flush(a, &st, 0);
+}
+
+__device__ __forceinline__ bool precedes(const uint32_t* __restrict__ key, int w, uint32_t kv, int v) {
+    const uint32_t kw = key[w];
+    return kw < kv || (kw == kv && w < v);
+}
+
+// Priority order, step 2: copy each row with the preceding neighbours first.
+template <int GS>
+__device__ __forceinline__ void reorder_group(const int* __restrict__ col, int* __restrict__ out,
+                                              int* __restrict__ split, const uint32_t* __restrict__ key,
+                                              int v, int s, int e, int lig, int lane) {
+    const uint32_t kv = key[v];
+    int nlo = 0;
+    for (int p0 = s; p0 < e; p0 += GS) {
+        const int p = p0 + lig;
+        const bool lo = (p < e) && precedes(key, col[p], kv, v);
+        nlo += __popcll(group_bits<GS>(__ballot(lo), lane));
+    }
+    int plo = s, phi = s + nlo;
+    const uint64_t below = (lig == 0) ? 0ull : ((1ull << lig) - 1ull);
+    for (int p0 = s; p0 < e; p0 += GS) {
+        const int p = p0 + lig;
+        int w = 0;
+        bool lo = false;
+        if (p < e) {
+            w = col[p];
+            lo = precedes(key, w, kv, v);
+        }
+        const uint64_t blo = group_bits<GS>(__ballot(p < e && lo), lane);
+        const uint64_t bhi = group_bits<GS>(__ballot(p < e && !lo), lane);
+        if (p < e) {
+            if (lo) out[plo + __popcll(blo & below)] = w;
+            else out[phi + __popcll(bhi & below)] = w;
+        }
+        plo += __popcll(blo);
+        phi += __popcll(bhi);
+    }
+    if (lig == 0) split[v] = nlo;
+}
+
+template <int GS>
+__device__ __forceinline__ void reorder_chunk(const Args& a, const int* col, int* out, int* split,
+                                              const uint32_t* key, const int* list, int cnt, int local) {
+    constexpr int CV = kBlock / GS;
+    const int lane = __lane_id();
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    if (idx < cnt) {
+        const int v = list[idx];
+        reorder_group<GS>(col, out, split, key, v, a.row_ptr[v], a.row_ptr[v + 1], lig, lane);
+    }
+}
+
+// One workgroup per hub row: two passes of 256-entry tiles with a block-wide
+// exclusive count of the preceding neighbours.
+__device__ void reorder_hub(const Args& a, const int* __restrict__ col, int* __restrict__ out,
+                            int* __restrict__ split, const uint32_t* __restrict__ key, int v, int* sh) {
+    const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+    const int lane = __lane_id();
+    const int wid = threadIdx.x / kWave;
+    const uint32_t kv = key[v];
+    const uint64_t below = __lanemask_lt();
+    int nlo = 0;
+    for (int p0 = s; p0 < e; p0 += kBlock) {
+        const int p = p0 + (int)threadIdx.x;
+        const bool lo = (p < e) && precedes(key, col[p], kv, v);
+        nlo += __syncthreads_count(lo);
+    }
+    int plo = s, phi = s + nlo;
+    for (int p0 = s; p0 < e; p0 += kBlock) {
+        const int p = p0 + (int)threadIdx.x;
+        int w = 0;
+        bool lo = false;
+        if (p < e) {
+            w = col[p];
+            lo = precedes(key, w, kv, v);
+        }
+        const uint64_t blo = __ballot(p < e && lo);
+        const uint64_t bhi = __ballot(p < e && !lo);
+        if (lane == 0) {
+            sh[wid] = __popcll(blo);
+            sh[4 + wid] = __popcll(bhi);
+        }
+        __syncthreads();
+        int olo = 0, ohi = 0, tlo = 0, thi = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) {
+            if (k < wid) {
+                olo += sh[k];
+                ohi += sh[4 + k];
+            }
+            tlo += sh[k];
+            thi += sh[4 + k];
+        }
+        __syncthreads();
+        if (p < e) {
+            if (lo) out[plo + olo + __popcll(blo & below)] = w;
+            else out[phi + ohi + __popcll(bhi & below)] = w;
+        }
+        plo += tlo;
+        phi += thi;
+    }
+    if (threadIdx.x == 0) split[v] = nlo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reorder(Args a, const int* __restrict__ col, int* __restrict__ out,
+                                                    int* __restrict__ split, const uint32_t* __restrict__ key) {
+    __shared__ int sh[16];
+    const ChunkMap m = make_map(a.ctl, 0);
+    for (int c = blockIdx.x; c < m.total; c += gridDim.x) {
+        const int b = chunk_bin(m, c);
+        const int local = c - m.start[b];
+        const int* list = list_ptr(a, 0, b);
+        switch (b) {
+            case 0: reorder_chunk<1>(a, col, out, split, key, list, m.cnt[0], local); break;
+            case 1: reorder_chunk<4>(a, col, out, split, key, list, m.cnt[1], local); break;
+            case 2: reorder_chunk<16>(a, col, out, split, key, list, m.cnt[2], local); break;
+            case 3: reorder_chunk<64>(a, col, out, split, key, list, m.cnt[3], local); break;
+            default: reorder_hub(a, col, out, split, key, list[local], sh); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Validation (opt-in) and statistics.
+// ---------------------------------------------------------------------------
+
+enum : int { kErrRowPtr = 1, kErrColRange = 2, kErrUnsorted = 4, kErrAsym = 8 };
+
+__global__ __launch_bounds__(kBlock) void k_validate_rows(int n, int nnz, const int* __restrict__ row_ptr,
+                                                          Ctl* ctl) {
+    int bad = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v <= n; v += gridDim.x * kBlock) {
+        const int r = row_ptr[v];
+        if (r < 0 || r > nnz) bad |= kErrRowPtr;
+        if (v == 0 && r != 0) bad |= kErrRowPtr;
+        if (v < n && row_ptr[v + 1] < r) bad |= kErrRowPtr;
+    }
+    if (bad) atomicOr(&ctl->err, bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_cols(int n, const int* __restrict__ row_ptr,
+                                                          const int* __restrict__ col, int need_sorted,
+                                                          Ctl* ctl) {
+    int bad = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        for (int p = s; p < e; ++p) {
+            const int w = col[p];
+            if (w < 0 || w >= n) {
+                bad |= kErrColRange;
+                continue;
+            }
+            if (p > s && col[p - 1] > w) bad |= kErrUnsorted;
+        }
+    }
+    if (bad) atomicOr(&ctl->err, bad);
+    (void)need_sorted;
+}
+
+// Symmetry: every entry (v, w) needs v in row w.  Rows are sorted (checked
+// first), so a binary search decides it.
+__global__ __launch_bounds__(kBlock) void k_validate_sym(int n, const int* __restrict__ row_ptr,
+                                                         const int* __restrict__ col, Ctl* ctl) {
+    int bad = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        for (int p = s; p < e; ++p) {
+            const int w = col[p];
+            int lo = row_ptr[w], hi = row_ptr[w + 1];
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (col[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo >= row_ptr[w + 1] || col[lo] != v) bad |= kErrAsym;
+        }
+    }
+    if (bad) atomicOr(&ctl->err, bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_maxcolor(int n, const int* __restrict__ color, Ctl* ctl) {
+    int mx = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) mx = max(mx, color[v]);
+    for (int o = kWave / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+    if (__lane_id() == 0 && mx) atomicMax(&ctl->maxcolor, mx);
+}
+
+__global__ void k_zero_ctl(Ctl* ctl) {
+    int* p = reinterpret_cast<int*>(ctl);
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, colp, total;
+};
+
+Layout layout(int32_t n, int64_t nnz) {
+    Layout L;
+    const size_t vn = sizeof(int32_t) * (size_t)n;
+    size_t off = 0;
+    L.ctl = off;   off += align_up(sizeof(Ctl));
+    L.log = off;   off += align_up(sizeof(int64_t) * kLogW * (size_t)kMaxLog);
+    L.tent = off;  off += align_up(vn);
+    L.told = off;  off += align_up(vn);
+    L.conf = off;  off += align_up(vn);
+    L.stamp = off; off += align_up(vn);
+    L.cflag = off; off += align_up(vn);
+    L.split = off; off += align_up(vn);
+    L.lists = off; off += align_up(vn * kSets * kBins);
+    L.colp = off;  off += align_up(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    L.total = off;
+    return L;
+}
+
+struct DeviceCache {
+    void* ws = nullptr;
+    size_t bytes = 0;
+    int cus = 0;
+};
+
+std::mutex g_mu;
+std::vector<DeviceCache> g_dev;
+
+// Process-wide tuning: degree-bin limits and blocks per CU of the grids.
+int g_bins[4] = {8, 32, 128, 2048};
+int g_blocks_per_cu = 8;
+
+// Optional per-kernel timing with HIP events recorded around each launch.
+enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfKinds = 5 };
+bool g_prof = false;
+double g_prof_ms[kProfKinds] = {};
+int64_t g_prof_launches[kProfKinds] = {};
+
+struct EventPairs {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+    hipError_t next(hipEvent_t* a, hipEvent_t* b, int k) {
+        while (ev.size() < 2 * (used + 1)) {
+            hipEvent_t e;
+            hipError_t rc = hipEventCreate(&e);
+            if (rc != hipSuccess) return rc;
+            ev.push_back(e);
+        }
+        if (kind.size() < used + 1) kind.resize(used + 1);
+        kind[used] = k;
+        *a = ev[2 * used];
+        *b = ev[2 * used + 1];
+        ++used;
+        return hipSuccess;
+    }
+};
+
+int32_t* pinned_buffer() {
+    thread_local int32_t* buf = nullptr;
+    if (!buf) {
+        if (hipHostMalloc((void**)&buf, 256, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    }
+    return buf;
+}
+
+#define GC_CHECK(x)                                \
+    do {                                           \
+        if ((x) != hipSuccess) return GCOLOR_EHIP; \
+    } while (0)
+
+BinCfg current_bins() {
+    std::lock_guard<std::mutex> g(g_mu);
+    BinCfg c;
+    for (int i = 0; i < 4; ++i) c.dmax[i] = g_bins[i];
+    return c;
+}
+
+int device_cus(int dev) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    if (!g_dev[dev].cus) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        g_dev[dev].cus = cus;
+    }
+    return g_dev[dev].cus;
+}
+
+int library_workspace(int dev, size_t need, void** out) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    DeviceCache& d = g_dev[dev];
+    if (d.bytes < need) {
+        if (d.ws) {
+            if (hipFree(d.ws) != hipSuccess) return GCOLOR_EHIP;
+            d.ws = nullptr;
+            d.bytes = 0;
+        }
+        if (hipMalloc(&d.ws, need) != hipSuccess) {
+            d.ws = nullptr;
+            return GCOLOR_EHIP;
+        }
+        d.bytes = need;
+    }
+    *out = d.ws;
+    return GCOLOR_OK;
+}
+
+// Launch with optional HIP events around it.
+struct Launcher {
+    hipStream_t st;
+    bool prof;
+    EventPairs* evp;
+    template <typename F>
+    hipError_t operator()(int kind, F&& launch) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            hipError_t rc = evp->next(&e0, &e1, kind);
+            if (rc != hipSuccess) return rc;
+            rc = hipEventRecord(e0, st);
+            if (rc != hipSuccess) return rc;
+        }
+        launch();
+        hipError_t rc = hipGetLastError();
+        if (rc != hipSuccess) return rc;
+        if (prof) return hipEventRecord(e1, st);
+        return hipSuccess;
+    }
+};
+
+int validate(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx, Ctl* ctl, int grid,
+             int32_t* host, hipStream_t st) {
+    k_validate_rows<<<grid, kBlock, 0, st>>>(n, (int)nnz, row_ptr, ctl);
+    GC_CHECK(hipGetLastError());
+    GC_CHECK(hipMemcpyAsync(host, &ctl->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    if (host[0]) return GCOLOR_ECSR;
+    k_validate_cols<<<grid, kBlock, 0, st>>>(n, row_ptr, col_idx, 1, ctl);
+    GC_CHECK(hipGetLastError());
+    GC_CHECK(hipMemcpyAsync(host, &ctl->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    if (host[0]) return GCOLOR_ECSR;
+    k_validate_sym<<<grid, kBlock, 0, st>>>(n, row_ptr, col_idx, ctl);
+    GC_CHECK(hipGetLastError());
+    GC_CHECK(hipMemcpyAsync(host, &ctl->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    if (host[0]) return GCOLOR_ECSR;
+    return GCOLOR_OK;
+}
+
+int sum_counts(const int32_t* h) {
+    int t = 0;
+    for (int b = 0; b < kBins; ++b) t += h[b];
+    return t;
+}
+
+int run_plain(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st) {
+    int k = 0;
+    int batch = 4;
+    for (;;) {
+        for (int j = 0; j < batch; ++j, ++k) {
+            const int side = k & 1;
+            GC_CHECK(L(kProfPhase1, [&] { k_phase1<<<grid, kBlock, 0, st>>>(a, side, k); }));
+            GC_CHECK(L(kProfPhase2, [&] { k_phase2<<<grid, kBlock, 0, st>>>(a, side, k); }));
+        }
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[k & 1][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        if (sum_counts(host) == 0) return GCOLOR_OK;
+        if (k > n + 64) return GCOLOR_EROUNDS;
+        batch = std::min(batch * 2, 16);
+    }
+}
+
+int run_incremental(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st) {
+    GC_CHECK(L(kProfIncC, [&] { k_inc_c<<<grid, kBlock, 0, st>>>(a, 1); }));
+    int k = 2;
+    int batch = 4;
+    for (;;) {
+        for (int j = 0; j < batch; ++j, ++k) {
+            GC_CHECK(L(kProfIncA, [&] { k_inc_a<<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncB, [&] { k_inc_b<<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncC, [&] { k_inc_c<<<grid, kBlock, 0, st>>>(a, k); }));
+        }
+        // dirty list of the next round k: empty exactly when every vertex is committed
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dset(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        if (sum_counts(host) == 0) break;
+        if (k > n + 64) return GCOLOR_EROUNDS;
+        batch = std::min(batch * 2, 16);
+    }
+    unsigned long long committed = 0;
+    GC_CHECK(hipMemcpyAsync(&committed, &a.ctl->committed, sizeof(committed), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    return committed == (unsigned long long)n ? GCOLOR_OK : GCOLOR_EINTERNAL;
+}
+
+int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                 const uint32_t* priority, int32_t* colors, void* ws, uint32_t flags,
+                 gcolor_stats_t* stats, gcolor_round_t* round_log, int32_t max_log, hipStream_t st) {
+    int dev = 0;
+    GC_CHECK(hipGetDevice(&dev));
+    const int cus = device_cus(dev);
+    const Layout Lw = layout(n, nnz);
+    char* base = static_cast<char*>(ws);
+    Ctl* ctl = reinterpret_cast<Ctl*>(base + Lw.ctl);
+    long long* log = reinterpret_cast<long long*>(base + Lw.log);
+    int32_t* host = pinned_buffer();
+    if (!host) return GCOLOR_EHIP;
+    const bool plain = (flags & GCOLOR_PLAIN) != 0;
+    const bool natural = priority == nullptr;
+    int grid;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        grid = cus * g_blocks_per_cu;
+    }
+
+    k_zero_ctl<<<1, 64, 0, st>>>(ctl);
+    GC_CHECK(hipGetLastError());
+    if (flags & GCOLOR_VALIDATE) {
+        const int rc = validate(n, nnz, row_ptr, col_idx, ctl, grid, host, st);
+        if (rc) return rc;
+    }
+
+    Args a;
+    a.n = n;
+    a.row_ptr = row_ptr;
+    a.colp = col_idx;
+    a.split = reinterpret_cast<int*>(base + Lw.split);
+    a.color = colors;
+    a.tent = reinterpret_cast<int*>(base + Lw.tent);
+    a.told = reinterpret_cast<int*>(base + Lw.told);
+    a.conf = reinterpret_cast<int*>(base + Lw.conf);
+    a.stamp = reinterpret_cast<int*>(base + Lw.stamp);
+    a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
+    a.lists = reinterpret_cast<int*>(base + Lw.lists);
+    a.ctl = ctl;
+    a.log = log;
+    a.cfg = current_bins();
+
+    const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    if (!natural) {
+        // rows reordered so that the neighbours preceding v come first
+        int* colp = reinterpret_cast<int*>(base + Lw.colp);
+        k_setup_bins<<<vgrid, kBlock, 0, st>>>(a);
+        GC_CHECK(hipGetLastError());
+        k_reorder<<<grid, kBlock, 0, st>>>(a, col_idx, colp, a.split, priority);
+        GC_CHECK(hipGetLastError());
+        a.colp = colp;
+    }
+
+    thread_local EventPairs evp;
+    evp.used = 0;
+    Launcher L{st, g_prof, &evp};
+    int rc;
+    if (plain) {
+        if (natural) {
+            k_setup_natural<<<vgrid, kBlock, 0, st>>>(a, a.split);
+            GC_CHECK(hipGetLastError());
+        }
+        rc = run_plain(a, n, grid, L, host, st);
+    } else {
+        k_inc_seed<<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+        GC_CHECK(hipGetLastError());
+        rc = run_incremental(a, n, grid, L, host, st);
+    }
+    if (rc) return rc;
+
+    if (L.prof) {
+        GC_CHECK(hipStreamSynchronize(st));
+        std::lock_guard<std::mutex> g(g_mu);
+        for (size_t i = 0; i < evp.used; ++i) {
+            float ms = 0.f;
+            GC_CHECK(hipEventElapsedTime(&ms, evp.ev[2 * i], evp.ev[2 * i + 1]));
+            g_prof_ms[evp.kind[i]] += ms;
+            g_prof_launches[evp.kind[i]] += 1;
+        }
+    }
+
+    if (stats || round_log) {
+        k_maxcolor<<<grid, kBlock, 0, st>>>(n, colors, ctl);
+        GC_CHECK(hipGetLastError());
+        Ctl hc;
+        GC_CHECK(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        const int rounds = hc.rounds;
+        const int nl = std::min(rounds, kMaxLog);
+        std::vector<long long> hl(kLogW * (size_t)std::max(nl, 1), 0);
+        if (nl > 0)
+            GC_CHECK(hipMemcpyAsync(hl.data(), log, sizeof(long long) * kLogW * (size_t)nl, hipMemcpyDeviceToHost,
+                                    st));
+        GC_CHECK(hipStreamSynchronize(st));
+        // per round: worklist size and its degree sum
+        std::vector<long long> U(nl), E(nl), C(nl, 0), D(nl, 0), DE(nl, 0);
+        if (plain) {
+            for (int r = 0; r < nl; ++r) {
+                U[r] = hl[kLogW * r];
+                E[r] = hl[kLogW * r + 1];
+                C[r] = U[r] - (r + 1 < nl ? hl[kLogW * (r + 1)] : 0);
+            }
+        } else {
+            long long u = n, e = nnz;
+            for (int r = 0; r < nl; ++r) {
+                U[r] = u;
+                E[r] = e;
+                C[r] = hl[kLogW * r];
+                D[r] = hl[kLogW * r + 2];
+                DE[r] = hl[kLogW * r + 3];
+                u -= hl[kLogW * r];
+                e -= hl[kLogW * r + 1];
+            }
+        }
+        if (stats) {
+            stats->rounds = rounds;
+            stats->num_colors = hc.maxcolor;
+            long long ew = 0;
+            for (int r = 0; r < nl; ++r) ew += E[r];
+            stats->edge_work = ew;
+            stats->status = 0;
+            stats->reserved = 0;
+        }
+        if (round_log) {
+            for (int r = 0; r < std::min(nl, max_log); ++r) {
+                round_log[r].round = r + 1;
+                round_log[r].worklist = U[r];
+                round_log[r].edge_work = E[r];
+                round_log[r].committed = C[r];
+                round_log[r].dirty = D[r];
+                round_log[r].dirty_edges = DE[r];
+            }
+        }
+    }
+    return GCOLOR_OK;
+}
+
+int read_nnz(int32_t n, const int32_t* row_ptr, hipStream_t st, int64_t* nnz) {
+    int32_t* host = pinned_buffer();
+    if (!host) return GCOLOR_EHIP;
+    GC_CHECK(hipMemcpyAsync(host, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    *nnz = host[0];
+    return GCOLOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gcolor_workspace_bytes(int32_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return layout(n, nnz).total;
+}
+
+int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* priority,
+                   int32_t* colors_out, void* workspace, size_t ws_bytes, uint32_t flags,
+                   gcolor_stats_t* stats, gcolor_round_t* round_log, int32_t max_log, gcolor_stream_t stream) {
+    if (n < 0) return GCOLOR_EINVAL;
+    if (flags & ~(uint32_t)(GCOLOR_VALIDATE | GCOLOR_STATS | GCOLOR_PLAIN)) return GCOLOR_EINVAL;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (n == 0) return GCOLOR_OK;
+    if (!row_ptr || !colors_out) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int64_t nnz = 0;
+    int rc = read_nnz(n, row_ptr, st, &nnz);
+    if (rc) return rc;
+    if (nnz < 0) return GCOLOR_ECSR;
+    if (nnz > 0 && !col_idx) return GCOLOR_EINVAL;
+    const size_t need = gcolor_workspace_bytes(n, nnz);
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < need) return GCOLOR_EWORKSPACE;
+    } else {
+        int dev = 0;
+        GC_CHECK(hipGetDevice(&dev));
+        rc = library_workspace(dev, need, &ws);
+        if (rc) return rc;
+    }
+    rc = run_coloring(n, nnz, row_ptr, col_idx, priority, colors_out, ws, flags, stats, round_log, max_log, st);
+    if (stats) stats->status = rc;
+    return rc;
+}
+
+int color_graph(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* priority,
+                int32_t* colors_out, gcolor_stream_t stream) {
+    return color_graph_ex(n, row_ptr, col_idx, priority, colors_out, nullptr, 0, 0, nullptr, nullptr, 0, stream);
+}
+
+const char* gcolor_strerror(int code) {
+    switch (code) {
+        case GCOLOR_OK: return "ok";
+        case GCOLOR_EINVAL: return "invalid argument";
+        case GCOLOR_ECSR: return "malformed CSR";
+        case GCOLOR_EWORKSPACE: return "workspace too small";
+        case GCOLOR_EHIP: return "HIP runtime error";
+        case GCOLOR_EROUNDS: return "round cap exceeded";
+        case GCOLOR_ENOTSUP: return "unsupported size";
+        case GCOLOR_EINTERNAL: return "internal consistency check failed";
+        default: return "unknown error";
+    }
+}
+
+const char* gcolor_version(void) { return "gcolor 0.2 (gfx950)"; }
+
+int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu) {
+    if (bin_limits) {
+        for (int i = 0; i < 4; ++i)
+            if (bin_limits[i] < 0 || (i > 0 && bin_limits[i] < bin_limits[i - 1])) return GCOLOR_EINVAL;
+    }
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    if (bin_limits)
+        for (int i = 0; i < 4; ++i) g_bins[i] = bin_limits[i];
+    if (blocks_per_cu > 0) g_blocks_per_cu = blocks_per_cu;
+    return GCOLOR_OK;
+}
+
+int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (bin_limits)
+        for (int i = 0; i < 4; ++i) bin_limits[i] = g_bins[i];
+    if (blocks_per_cu) *blocks_per_cu = g_blocks_per_cu;
+    return GCOLOR_OK;
+}
+
+int gcolor_profile(int32_t enable) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_prof = enable != 0;
+    for (int i = 0; i < kProfKinds; ++i) {
+        g_prof_ms[i] = 0;
+        g_prof_launches[i] = 0;
+    }
+    return GCOLOR_OK;
+}
+
+int gcolor_profile_read(int32_t kernel, double* total_ms, int64_t* launches) {
+    if (kernel < 0 || kernel >= kProfKinds) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    if (total_ms) *total_ms = g_prof_ms[kernel];
+    if (launches) *launches = g_prof_launches[kernel];
+    return GCOLOR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""The C ABI library loads, exports every symbol its headers declare, and its
+host-side argument checks behave as documented.  No test here launches GPU
+work: the calls below return before any HIP call is made."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\**\s+\**\s*([A-Za-z_]\w*)\s*\([^;{]*\)\s*;",
+                             text, flags=re.M):
+            names.append(m.group(1))
+    return names
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("color_graph", "color_graph_ex", "gcolor_workspace_bytes", "gcolor_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1205_3809_amd as gc
+    lib = ctypes.CDLL(gc.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_no_cpu_fallback_when_library_missing(tmp_path):
+    """Importing the binding without the built library raises instead of
+    falling back to anything else."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r); import paper_1205_3809_amd._binding as b" % ROOT)
+    env = dict(os.environ)
+    # point the binding at an empty copy of the package
+    pkg = tmp_path / "paper_1205_3809_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "_binding.py"):
+        (pkg / f).write_text(open(os.path.join(ROOT, "paper_1205_3809_amd", f)).read())
+    code = "import sys; sys.path.insert(0, %r); import paper_1205_3809_amd" % str(tmp_path)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env)
+    assert r.returncode != 0 and "libgcolor.so is not built" in r.stderr
+
+
+def test_strerror_and_codes():
+    import paper_1205_3809_amd as gc
+    assert gc.strerror(0) == "ok"
+    assert gc.strerror(-1) == "invalid argument"
+    assert gc.strerror(-2) == "malformed CSR"
+    assert gc.strerror(-3) == "workspace too small"
+    assert gc.strerror(-5) == "round cap exceeded"
+    assert gc.strerror(-99) == "unknown error"
+
+
+def test_workspace_bytes_grows_with_size():
+    import paper_1205_3809_amd as gc
+    a = gc.workspace_bytes(1000, 5000)
+    b = gc.workspace_bytes(2000, 5000)
+    c = gc.workspace_bytes(2000, 50000)
+    assert 0 < a < b < c
+    # per vertex: tent, split and 10 worklist slots; per entry: the reordered row
+    assert b - a >= 48 * 1000 - 2048 and c - b >= 4 * 45000 - 256
+    assert gc.workspace_bytes(-1, 0) == 0
+
+
+def test_argument_errors_before_any_device_work():
+    import paper_1205_3809_amd as gc
+    lib = gc.raw_library()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
+    assert lib.color_graph(-1, fake, fake, None, fake, None) == -1
+    assert lib.color_graph(0, None, None, None, None, None) == 0  # empty graph: nothing to do
+    assert lib.color_graph(5, None, fake, None, fake, None) == -1
+    assert lib.color_graph(5, fake, fake, None, None, None) == -1
+    assert lib.color_graph_ex(5, fake, fake, None, fake, None, 0, 1 << 20, None, None, 0, None) == -1
+
+
+def test_tuning_validation():
+    import paper_1205_3809_amd as gc
+    old, bpc = gc.get_tuning()
+    with pytest.raises(gc.GColorError):
+        gc.set_tuning([8, 4, 16, 32])
+    with pytest.raises(gc.GColorError):
+        gc.set_tuning(None, 100)
+    gc.set_tuning([4, 16, 64, 1024], 4)
+    assert gc.get_tuning() == ([4, 16, 64, 1024], 4)
+    gc.set_tuning(old, bpc)
+    assert gc.get_tuning() == (old, bpc)

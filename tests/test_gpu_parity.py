@@ -1,0 +1,259 @@
+"""GPU colouring vs the CPU oracle, bit for bit, through the C ABI.
+
+Every case compares colors_out element by element with the oracle's
+round-synchronous simulation on the same seeded input, checks the round count,
+the colour count and the per-round worklist/edge-work log, and validates the
+colouring independently (adjacent vertices differ, colour <= degree + 1).
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def gpu_color(g, key=None, workspace=None, **kw):
+    import paper_1205_3809_amd as gc
+    rp, ci = dev(g.row_ptr), dev(g.col_idx)
+    pr = None if key is None else dev(np.ascontiguousarray(key, dtype=np.uint32).view(np.int32))
+    col, st = gc.color_graph_ex(rp, ci, pr, workspace=workspace, stats=True, max_log=1 << 16, **kw)
+    torch.cuda.synchronize()
+    return col.cpu().numpy(), st
+
+
+def valid(g, col):
+    src = np.repeat(np.arange(g.n), g.degrees())
+    return col.min(initial=1) >= 1 and not np.any(col[src] == col[g.col_idx]) and np.all(col <= g.degrees() + 1)
+
+
+# both engines compute the same function: the default incremental one and
+# the plain one that rescans every worklist row each round
+ENGINES = (("incremental", 0), ("plain", 4))
+
+
+def check(g, key=None, label="", engines=ENGINES):
+    ref = oracle.spec_sim(g.row_ptr, g.col_idx, key, threads=0)
+    out = None
+    for name, flags in engines:
+        print("case %s engine=%s n=%d nnz=%d key=%s" % (label, name, g.n, g.nnz,
+                                                         None if key is None else key.dtype), flush=True)
+        col, st = gpu_color(g, key, flags=flags)
+        assert col.shape == ref.colors.shape
+        mism = np.flatnonzero(col != ref.colors)
+        assert mism.size == 0, "%s: %d mismatches, first at %s" % (name, mism.size, mism[:5])
+        assert valid(g, col)
+        assert st.rounds == ref.rounds, name
+        assert st.num_colors == (int(ref.colors.max()) if g.n else 0)
+        assert st.edge_work == int(ref.log[:, 2].sum()), name
+        got = np.array([[k, u, e] for k, u, e in st.round_log], dtype=np.int64).reshape(-1, 3)
+        assert np.array_equal(got, ref.log[:, :3]), name
+        committed = np.array([d[0] for d in st.detail], dtype=np.int64)
+        assert np.array_equal(committed, ref.log[:, 1] - ref.log[:, 3]), name
+        out = (col, st) if out is None else out
+    return out
+
+
+# ---------------------------------------------------------------------------
+# structured graphs and closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 300, 1001])
+def test_empty_graph(n):
+    col, st = check(graphgen.empty(n), label="empty")
+    assert st.rounds == 1 and np.all(col == 1)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 63, 64, 65, 257, 1000])
+def test_paths_and_cycles(n):
+    check(graphgen.path(n), label="path")
+    if n >= 3:
+        check(graphgen.cycle(n), label="cycle")
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 66, 129, 130, 200, 300])
+def test_complete_graphs_many_windows(n):
+    """K_n needs n colours: more than one 64-colour window from n = 64 on."""
+    col, st = check(graphgen.complete(n), label="complete")
+    assert st.num_colors == n and st.rounds == n
+
+
+@pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (70000, 123)])
+def test_star_hubs(n, center):
+    """A centre of degree up to 70k runs on the workgroup-per-vertex bin."""
+    check(graphgen.star(n, center), label="star")
+
+
+@pytest.mark.parametrize("shape,full", [((64, 64), False), ((37, 41), True), ((16, 16, 16), False),
+                                        ((9, 10, 11), True)])
+def test_grids(shape, full):
+    col, st = check(graphgen.grid(shape, full), label="grid")
+    if not full:
+        assert st.num_colors == 2
+
+
+def test_grid_with_extra_edges_and_rgg():
+    check(graphgen.grid_with_extra((90, 90), False, 0.05, 1), label="grid+extra")
+    check(graphgen.rgg(20000, 15.0, 2), label="rgg")
+
+
+# ---------------------------------------------------------------------------
+# random graphs, several orders
+# ---------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def rmat(scale, ef, abc, seed):
+    return graphgen.rmat(scale, ef, abc, seed)
+
+
+def test_uniform_config():
+    """2^14 vertices, 2^17 uniform pairs, natural order."""
+    check(graphgen.uniform(1 << 14, 1 << 17, 1), label="uniform")
+
+
+@pytest.mark.parametrize("abc", [(0.25, 0.25, 0.25), (0.45, 0.15, 0.15), (0.55, 0.1, 0.1), (0.55, 0.15, 0.15)])
+def test_rmat_small_natural(abc):
+    check(rmat(14, 8, abc, 3), label="rmat14")
+
+
+@pytest.mark.parametrize("order", ["perm", "ties3", "ties12", "allsame"])
+def test_rmat_small_priorities(order):
+    g = rmat(14, 8, (0.55, 0.1, 0.1), 3)
+    if order == "perm":
+        key = graphgen.random_priority(g.n, 8)
+    elif order == "allsame":
+        key = np.full(g.n, 7, dtype=np.uint32)
+    else:
+        key = graphgen.random_keys(g.n, 9, bits=int(order[4:]))
+    check(g, key, label="rmat14-" + order)
+
+
+def test_priority_identity_equals_natural():
+    g = rmat(14, 8, (0.45, 0.15, 0.15), 4)
+    a, _ = gpu_color(g)
+    b, _ = gpu_color(g, np.arange(g.n, dtype=np.uint32))
+    assert np.array_equal(a, b)
+
+
+def test_unsorted_rows_with_priority():
+    """With a priority array the rows may come in any order."""
+    g = rmat(12, 8, (0.55, 0.1, 0.1), 5)
+    rng = np.random.default_rng(0)
+    col = g.col_idx.copy()
+    for v in range(g.n):
+        s, e = g.row_ptr[v], g.row_ptr[v + 1]
+        col[s:e] = rng.permutation(col[s:e])
+    h = graphgen.CSR(g.n, g.row_ptr, col)
+    key = graphgen.random_priority(g.n, 1)
+    ref = oracle.spec_sim(g.row_ptr, g.col_idx, key)
+    got, _ = gpu_color(h, key)
+    assert np.array_equal(got, ref.colors)
+
+
+# ---------------------------------------------------------------------------
+# launch-shape independence, determinism, workspace handling, streams
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", [0, 4], ids=["incremental", "plain"])
+def test_result_independent_of_tuning(engine):
+    import paper_1205_3809_amd as gc
+    g = rmat(15, 8, (0.55, 0.1, 0.1), 6)
+    key = graphgen.random_priority(g.n, 2)
+    ref = oracle.spec_sim(g.row_ptr, g.col_idx, key, threads=0).colors
+    refn = oracle.spec_sim(g.row_ptr, g.col_idx, None, threads=0).colors
+    old, bpc = gc.get_tuning()
+    try:
+        for bins, b in [([0, 0, 0, 0], 2), ([1, 2, 3, 4], 1), ([64, 64, 64, 64], 16), ([2, 8, 64, 256], 8),
+                        ([1000000] * 4, 3)]:
+            gc.set_tuning(bins, b)
+            got, _ = gpu_color(g, key, flags=engine)
+            assert np.array_equal(got, ref), (bins, b)
+            got, _ = gpu_color(g, None, flags=engine)
+            assert np.array_equal(got, refn), (bins, b)
+    finally:
+        gc.set_tuning(old, bpc)
+
+
+def test_repeatable():
+    g = rmat(16, 8, (0.55, 0.1, 0.1), 7)
+    runs = [gpu_color(g)[0] for _ in range(3)] + [gpu_color(g, flags=4)[0] for _ in range(2)]
+    assert all(np.array_equal(runs[0], r) for r in runs[1:])
+
+
+def test_caller_workspace_and_shrinking_inputs():
+    import paper_1205_3809_amd as gc
+    big = rmat(14, 8, (0.45, 0.15, 0.15), 1)
+    small = graphgen.uniform(5000, 20000, 3)
+    ws = torch.empty(gc.workspace_bytes(big.n, big.nnz), dtype=torch.uint8, device="cuda")
+    for g in (big, small, big):
+        got, _ = gpu_color(g, workspace=ws)
+        assert np.array_equal(got, oracle.spec_sim(g.row_ptr, g.col_idx).colors)
+    with pytest.raises(gc.GColorError) as e:
+        gpu_color(big, workspace=ws[:1000])
+    assert e.value.code == -3
+
+
+def test_plain_entry_point_on_side_stream():
+    import paper_1205_3809_amd as gc
+    g = graphgen.uniform(1 << 14, 1 << 17, 5)
+    s = torch.cuda.Stream()
+    rp, ci = dev(g.row_ptr), dev(g.col_idx)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out = gc.color_graph(rp, ci)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.spec_sim(g.row_ptr, g.col_idx).colors)
+
+
+# ---------------------------------------------------------------------------
+# validation of malformed input (host-forced error paths)
+# ---------------------------------------------------------------------------
+
+def _validate(rp, ci, key=None):
+    import paper_1205_3809_amd as gc
+    with pytest.raises(gc.GColorError) as e:
+        gc.color_graph_ex(dev(rp), dev(ci), None if key is None else dev(key), flags=gc.FLAG_VALIDATE)
+    return e.value.code
+
+
+def test_validate_rejects_malformed_csr():
+    g = graphgen.cycle(10)
+    rp, ci = g.row_ptr.copy(), g.col_idx.copy()
+    bad = ci.copy(); bad[3] = 10
+    assert _validate(rp, bad) == -2           # neighbour id out of range
+    bad = ci.copy(); bad[0], bad[1] = bad[1], bad[0]
+    assert _validate(rp, bad) == -2           # unsorted row
+    bad = ci.copy(); bad[2] = 5
+    assert _validate(rp, bad) == -2           # asymmetric
+    badr = rp.copy(); badr[4] = badr[6]
+    assert _validate(badr, ci) == -2          # row_ptr not monotone
+    import paper_1205_3809_amd as gc
+    out, _ = gc.color_graph_ex(dev(rp), dev(ci), flags=gc.FLAG_VALIDATE)
+    assert np.array_equal(out.cpu().numpy(), oracle.spec_sim(rp, ci).colors)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("abc", [(0.25, 0.25, 0.25), (0.45, 0.15, 0.15)])
+def test_rmat_scale20_natural(abc):
+    """R-MAT scale 20, edge factor 8, ER-like and skewed parameters."""
+    check(rmat(20, 8, abc, 11), label="rmat20")
+
+
+@pytest.mark.parametrize("order", ["natural", "perm"])
+def test_rmat_scale24(order):
+    """R-MAT scale 24, edge factor 8, (0.55, 0.1, 0.1, 0.25): the full
+    benchmark workload, compared on every vertex."""
+    g = rmat(24, 8, (0.55, 0.1, 0.1), 11)
+    key = None if order == "natural" else graphgen.random_priority(g.n, 12)
+    check(g, key, label="rmat24-" + order)
