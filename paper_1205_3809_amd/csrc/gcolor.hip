@@ -60,7 +60,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kBins = 5;
-constexpr int kSets = 4;          // list sets: 0,1 = worklist/dirty ping-pong, 2,3 = candidates
+constexpr int kSets = 6;          // list sets (plain: 0,1 worklist ping-pong; incremental: see below)
 constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
 constexpr int kLogW = 4;          // int64 words per logged round
 
@@ -83,15 +83,15 @@ struct BinCfg {
 };
 
 struct Ctl {
-    int32_t cnt[kSets][8];  // [list set][bin] list lengths
+    int32_t cnt[8][8];      // [list set][bin] list lengths
     int32_t rounds;         // last round that committed a vertex
     int32_t err;            // validation error bits
     int32_t maxcolor;
-    int32_t pad0;
+    int32_t maxdeg;
     unsigned long long committed;  // vertices committed so far
     int32_t pad[10];
 };
-static_assert(sizeof(Ctl) == 192, "ctl layout");
+static_assert(sizeof(Ctl) == 320, "ctl layout");
 
 struct Args {
     int n;
@@ -99,12 +99,15 @@ struct Args {
     const int* __restrict__ colp;  // original col_idx, or the reordered copy
     int* __restrict__ split;       // entries at the front of each row that precede the vertex
     int* __restrict__ color;       // the caller's colors_out: 0 until committed
-    int* __restrict__ tent;        // tentative colour (incremental: 0 once committed)
-    int* __restrict__ told;        // (incremental) tentative colour before this round's change
+    int* __restrict__ tent;        // (plain) tentative colour
+    void* st;                      // (incremental) state words, int16_t or int32_t
+    void* stold;                   // (incremental) tentative colour before this round's change
     int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
     int* __restrict__ stamp;       // (incremental) round of last dirty mark
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
     int* __restrict__ lists;       // [kSets][kBins][n]
+    unsigned* __restrict__ dbits;  // (incremental) 3 dirty bitmaps of nwords words
+    int nwords;
     Ctl* ctl;
     long long* __restrict__ log;   // [kMaxLog][kLogW]
     BinCfg cfg;
@@ -183,11 +186,22 @@ __device__ __forceinline__ void stage_append(const Args& a, Stage* st, bool pred
     }
 }
 
+// Staged append of one vertex by one lane (sparse appends from inside row
+// loops): a per-lane LDS atomic, no wavefront-wide ballots.
+__device__ __forceinline__ void stage_push(const Args& a, Stage* st, int v, int deg, int set) {
+    const int k = bin_of(deg, a.cfg);
+    const int slot = atomicAdd(&st->cnt[k], 1);
+    if (slot < stage_cap(k)) {
+        st->q[stage_off(k) + slot] = v;
+    } else {
+        const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
+        list_ptr(a, set, k)[g] = v;
+    }
+}
+
 // Staged append where the degree must still be looked up.
 __device__ __forceinline__ void stage_append_lookup(const Args& a, Stage* st, bool pred, int v, int set) {
-    if (__ballot(pred) == 0) return;
-    const int deg = pred ? a.row_ptr[v + 1] - a.row_ptr[v] : 0;
-    stage_append(a, st, pred, v, deg, set);
+    if (pred) stage_push(a, st, v, a.row_ptr[v + 1] - a.row_ptr[v], set);
 }
 
 // Move the staged entries to the global lists (block-uniform call).
@@ -238,9 +252,13 @@ __device__ __forceinline__ ChunkMap make_map(const Ctl* ctl, int set) {
 }
 
 __device__ __forceinline__ int chunk_bin(const ChunkMap& m, int c) {
-    int b = kBins - 1;
-    while (b > 0 && c >= m.start[b - 1]) --b;
-    return b;
+    // bins occupy [start[4], start[3]), [start[3], start[2]), ... in that order
+    return 4 - (c >= m.start[3]) - (c >= m.start[2]) - (c >= m.start[1]) - (c >= m.start[0]);
+}
+
+// m.start[b] / m.cnt[b] without dynamic register indexing.
+__device__ __forceinline__ int pick5(const int* x, int b) {
+    return b == 0 ? x[0] : b == 1 ? x[1] : b == 2 ? x[2] : b == 3 ? x[3] : x[4];
 }
 
 // Smallest colour >= base not held by a committed neighbour in the row
@@ -300,9 +318,28 @@ __device__ __forceinline__ int first_fit_block(int s, int e, int base, const int
         const ChunkMap m_ = make_map((A).ctl, (SET));                                  \
         for (int c_ = blockIdx.x; c_ < m_.total; c_ += gridDim.x) {                     \
             const int b_ = chunk_bin(m_, c_);                                          \
-            const int local_ = c_ - m_.start[b_];                                      \
+            const int local_ = c_ - pick5(m_.start, b_);                                      \
             const int* list_ = list_ptr((A), (SET), b_);                               \
-            const int cnt_ = m_.cnt[b_];                                               \
+            const int cnt_ = pick5(m_.cnt, b_);                                               \
+            switch (b_) {                                                              \
+                case 0: BODY_GS(1, list_, cnt_, local_); break;                        \
+                case 1: BODY_GS(4, list_, cnt_, local_); break;                        \
+                case 2: BODY_GS(16, list_, cnt_, local_); break;                       \
+                case 3: BODY_GS(64, list_, cnt_, local_); break;                       \
+                default: BODY_BLOCK(list_[local_]); break;                             \
+            }                                                                          \
+            AFTER();                                                                   \
+        }                                                                              \
+    }
+
+// Same walk over a chunk map computed beforehand.
+#define GC_WALK_CHUNKS(A, M, SET, BODY_GS, BODY_BLOCK, AFTER)                          \
+    {                                                                                  \
+        for (int c_ = blockIdx.x; c_ < (M).total; c_ += gridDim.x) {                    \
+            const int b_ = chunk_bin((M), c_);                                         \
+            const int local_ = c_ - pick5((M).start, b_);                                     \
+            const int* list_ = list_ptr((A), (SET), b_);                               \
+            const int cnt_ = pick5((M).cnt, b_);                                              \
             switch (b_) {                                                              \
                 case 0: BODY_GS(1, list_, cnt_, local_); break;                        \
                 case 1: BODY_GS(4, list_, cnt_, local_); break;                        \
@@ -361,6 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_phase1(Args a, int side, int k) {
             }
         }
     }
+    const ChunkMap m = make_map(a.ctl, side);
+    if ((int)blockIdx.x >= m.total) return;
 #define P1_GS(GS, L, C, LOC) phase1_chunk<GS>(a, L, C, LOC)
 #define P1_BLOCK(V)                                                                                \
     {                                                                                              \
@@ -368,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_phase1(Args a, int side, int k) {
         const int t_ = first_fit_block(a.row_ptr[v_], a.row_ptr[v_ + 1], 1, a.colp, a.color, red); \
         if (threadIdx.x == 0) a.tent[v_] = t_;                                                     \
     }
-    GC_FOR_CHUNKS(a, side, P1_GS, P1_BLOCK, GC_NOTHING)
+    GC_WALK_CHUNKS(a, m, side, P1_GS, P1_BLOCK, GC_NOTHING)
 #undef P1_GS
 #undef P1_BLOCK
 }
@@ -435,13 +474,15 @@ __device__ __forceinline__ void phase2_block(const Args& a, Stage* st, int v, in
 // Phase 2 of round k: conflict detection, commit, compaction into side^1.
 __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
     __shared__ Stage st;
+    const ChunkMap m = make_map(a.ctl, side);
+    if ((int)blockIdx.x >= m.total) return;
     stage_init(&st);
     const int nside = side ^ 1;
     long long ework = 0;
 #define P2_GS(GS, L, C, LOC) phase2_chunk<GS>(a, &st, L, C, LOC, nside, &ework)
 #define P2_BLOCK(V) phase2_block(a, &st, (V), nside, &ework)
 #define P2_AFTER() stage_maybe_flush(a, &st, nside)
-    GC_FOR_CHUNKS(a, side, P2_GS, P2_BLOCK, P2_AFTER)
+    GC_WALK_CHUNKS(a, m, side, P2_GS, P2_BLOCK, P2_AFTER)
 #undef P2_GS
 #undef P2_BLOCK
 #undef P2_AFTER
@@ -451,22 +492,63 @@ __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
 
 // ===========================================================================
 // Incremental engine (rounds k = 1, 2, ...; round 1 needs only k_inc_c)
+//
+// One signed state word per vertex, S = int16_t when every colour fits
+// (max degree + 1 <= 32767), else int32_t:
+//   st[v] > 0   v is uncoloured, st[v] is its tentative colour
+//   st[v] < 0   v is committed with colour -st[v]
+// so a single gather of a neighbour's word answers every question a kernel
+// asks about it.  colors_out is written once, at commit.
+//
+// Round k:
+//   k_inc_a  for each dirty vertex w (tentative colour must move): one scan
+//            of its row gives the new tentative colour (first-fit over the
+//            committed words) and, from the same gathered words, the count
+//            of preceding clean neighbours holding the new colour; later
+//            clean neighbours holding the old or the new colour get their
+//            counters adjusted by -1 / +1.  Dirty neighbours are recognised
+//            in a one-bit-per-vertex bitmap (L2 resident).  A dirty vertex
+//            with a preceding dirty neighbour goes to k_inc_b.
+//   k_inc_b  adds, for those, the preceding dirty neighbours holding the
+//            same new colour (their new colours are final now).
+//   k_inc_c  commits every candidate whose counter is 0 and marks dirty
+//            each later neighbour holding the same tentative colour (a
+//            preceding one cannot: it would have kept the counter above 0).
+// List sets: dirty lists rotate over 3 sets (k % 3) with their bitmaps, so
+// the bits of round k-1 can be cleared during round k; candidate lists
+// alternate over 2 sets; one set holds the k_inc_b list.
 // ===========================================================================
 
-__host__ __device__ inline int dset(int k) { return k & 1; }
-__host__ __device__ inline int cset(int k) { return 2 + (k & 1); }
+constexpr int kSetCand = 3;  // + (k & 1)
+constexpr int kSetB = 5;
+
+__host__ __device__ inline int dlist(int k) { return k % 3; }
+__host__ __device__ inline int cset(int k) { return kSetCand + (k & 1); }
+
+__device__ __forceinline__ unsigned* dbits(const Args& a, int k) {
+    return a.dbits + (size_t)dlist(k) * (size_t)a.nwords;
+}
+
+__device__ __forceinline__ bool is_dirty(const unsigned* __restrict__ bits, int x) {
+    return (bits[x >> 5] >> (x & 31)) & 1u;
+}
 
 // Round-1 state: every tentative colour is 1, so conf[v] is the number of
 // preceding neighbours; vertices with none are the round-1 candidates.
 // Natural order (rows sorted): split[v] = lower_bound(row, v) - row start.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
-    __shared__ Stage st;
-    stage_init(&st);
+    __shared__ Stage stg;
+    stage_init(&stg);
+    S* st = static_cast<S*>(a.st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int b = 0; b < 8; ++b) a.ctl->cnt[dset(2)][b] = 0;  // held the set-up bins
+        for (int t = 0; t < kSetB + 1; ++t)
+            if (t != cset(1))
+                for (int b = 0; b < 8; ++b) a.ctl->cnt[t][b] = 0;
         for (int i = 0; i < kLogW; ++i) a.log[i] = 0;
     }
     const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < 3 * a.nwords; i += stride) a.dbits[i] = 0u;
     for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = base + (int)threadIdx.x;
         const bool ok = v < a.n;
@@ -486,85 +568,61 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
             } else {
                 sp = a.split[v];
             }
-            a.color[v] = 0;
-            a.tent[v] = 1;
-            a.told[v] = 0;
+            st[v] = 1;
             a.conf[v] = sp;
             a.stamp[v] = 0;
             a.cflag[v] = 0;
         }
-        stage_append(a, &st, ok && sp == 0, v, deg, cset(1));
-        stage_maybe_flush(a, &st, cset(1));
+        stage_append(a, &stg, ok && sp == 0, v, deg, cset(1));
+        stage_maybe_flush(a, &stg, cset(1));
     }
-    stage_flush(a, &st, cset(1));
+    stage_flush(a, &stg, cset(1));
 }
 
-// Round k: new tentative colours of the dirty vertices: first-fit over the
-// committed colours of the row.
-template <int GS>
-__device__ __forceinline__ void inc_a_chunk(const Args& a, const int* list, int cnt, int local) {
-    constexpr int CV = kBlock / GS;
-    const int lig = threadIdx.x & (GS - 1);
-    const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) {
-        const int u = list[idx];
-        const int t = first_fit_group<GS>(a.row_ptr[u], a.row_ptr[u + 1], lig, 1, a.colp, a.color);
-        if (lig == 0) {
-            a.told[u] = a.tent[u];
-            a.tent[u] = t;
-        }
+// Colours base..base+63 held by committed neighbours among the entries
+// start, start + STRIDE, ... < e of a row, read from the state words
+// (committed = negative); four independent gathers in flight per lane.
+template <int STRIDE, typename S>
+__device__ __forceinline__ uint64_t state_window(int start, int e, int base, const int* __restrict__ colp,
+                                                 const S* __restrict__ st) {
+    uint64_t m = 0;
+    int p = start;
+    for (; p + 3 * STRIDE < e; p += 4 * STRIDE) {
+        const int w0 = colp[p], w1 = colp[p + STRIDE], w2 = colp[p + 2 * STRIDE], w3 = colp[p + 3 * STRIDE];
+        const int x0 = st[w0], x1 = st[w1], x2 = st[w2], x3 = st[w3];
+        const unsigned c0 = (unsigned)(-x0 - base), c1 = (unsigned)(-x1 - base);
+        const unsigned c2 = (unsigned)(-x2 - base), c3 = (unsigned)(-x3 - base);
+        if (c0 < 64u) m |= 1ull << c0;
+        if (c1 < 64u) m |= 1ull << c1;
+        if (c2 < 64u) m |= 1ull << c2;
+        if (c3 < 64u) m |= 1ull << c3;
     }
+    for (; p < e; p += STRIDE) {
+        const unsigned c = (unsigned)(-(int)st[colp[p]] - base);
+        if (c < 64u) m |= 1ull << c;
+    }
+    return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
-    __shared__ uint64_t red[kBlock / kWave];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int b = 0; b < 8; ++b) {
-            a.ctl->cnt[dset(k + 1)][b] = 0;
-            a.ctl->cnt[cset(k)][b] = 0;
-        }
-        if (k - 1 < kMaxLog) {
-            long long nd = 0;
-            for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dset(k)][b];
-            a.log[kLogW * (k - 1) + 0] = 0;
-            a.log[kLogW * (k - 1) + 1] = 0;
-            a.log[kLogW * (k - 1) + 2] = nd;
-            a.log[kLogW * (k - 1) + 3] = 0;
-        }
-    }
-#define A_GS(GS, L, C, LOC) inc_a_chunk<GS>(a, L, C, LOC)
-#define A_BLOCK(V)                                                                                 \
-    {                                                                                              \
-        const int u_ = (V);                                                                        \
-        const int t_ = first_fit_block(a.row_ptr[u_], a.row_ptr[u_ + 1], 1, a.colp, a.color, red); \
-        if (threadIdx.x == 0) {                                                                    \
-            a.told[u_] = a.tent[u_];                                                               \
-            a.tent[u_] = t_;                                                                       \
-        }                                                                                          \
-    }
-    GC_FOR_CHUNKS(a, dset(k), A_GS, A_BLOCK, GC_NOTHING)
-#undef A_GS
-#undef A_BLOCK
-}
+// Row entries kept in registers: up to kCache per lane.
+constexpr int kCache = 8;
 
-// One row entry of a dirty vertex w (tentative colour changed old -> now):
-// the preceding part recounts w's own counter, the rest adjusts the counter
-// of each later neighbour x whose tentative colour equals old or now.  x's
-// own recount covers the case where x is dirty too; committed x hold
-// tentative colour 0 and never match.  Returns true when x's counter just
-// dropped to 0 and x was not yet a candidate this round.
-__device__ __forceinline__ bool inc_b_entry(const Args& a, int k, int w, int p, int lim, int now, int old,
-                                            int* cnt, int* xout) {
-    const int x = a.colp[p];
-    const int tx = a.tent[x];
-    *xout = x;
+// Evaluation of one entry (x with word sx at row position p) of dirty vertex
+// w after its new colour `now` is known.  Preceding clean neighbours count
+// toward w's counter; later clean neighbours holding old / now get -1 / +1
+// (returns true when such a counter just reached 0 for the first time in
+// this round: x becomes a candidate).  Dirty neighbours are skipped; a
+// preceding one sets *dlow (k_inc_b finishes w's count).
+__device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __restrict__ bits, int k, int w, int p,
+                                           int lim, int now, int old, int x, int sx, int* cnt, bool* dlow) {
     if (p < lim) {
-        *cnt += (tx == now);
+        if (is_dirty(bits, x)) *dlow = true;
+        else *cnt += (sx == now);
         return false;
     }
-    if (x == w || (tx != now && tx != old)) return false;
-    if (a.stamp[x] == k) return false;
-    if (tx == now) {
+    if (x == w || (sx != now && sx != old)) return false;
+    if (is_dirty(bits, x)) return false;
+    if (sx == now) {
         atomicAdd(&a.conf[x], 1);
         return false;
     }
@@ -572,47 +630,234 @@ __device__ __forceinline__ bool inc_b_entry(const Args& a, int k, int w, int p, 
     return atomicExch(&a.cflag[x], k) != k;
 }
 
-template <int GS>
-__device__ __forceinline__ void inc_b_chunk(const Args& a, Stage* st, int k, const int* list, int cnt, int local,
-                                            long long* dedges) {
-    constexpr int CV = kBlock / GS;
-    const int lig = threadIdx.x & (GS - 1);
-    const int idx = local * CV + (int)threadIdx.x / GS;
+// Second pass over a row too long for the register cache: re-gather.
+template <int STRIDE, typename S>
+__device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, const S* __restrict__ st,
+                                                   const unsigned* __restrict__ bits, int k, int w, int start, int e,
+                                                   int lim, int now, int old, int* cnt, bool* dlow) {
     const int cs = cset(k);
-    if (idx < cnt) {
-        const int w = list[idx];
-        const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
-        const int lim = s + a.split[w];
-        const int now = a.tent[w], old = a.told[w];
-        if (lig == 0) *dedges += e - s;
-        int c = 0;
-        for (int p = s + lig; p < e; p += GS) {
-            int x;
-            const bool cand = inc_b_entry(a, k, w, p, lim, now, old, &c, &x);
-            stage_append_lookup(a, st, cand, x, cs);
+    for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
+        int x[4], sx[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            x[j] = p < e ? a.colp[p] : w;
         }
-        c = group_sum<GS>(c);
-        bool cand = false;
-        if (lig == 0) {
-            a.conf[w] = c;
-            cand = (c == 0) && (atomicExch(&a.cflag[w], k) != k);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sx[j] = st[x[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            const bool cand = (p < e) && inc_a_eval(a, bits, k, w, p, lim, now, old, x[j], sx[j], cnt, dlow);
+            stage_append_lookup(a, stg, cand, x[j], cs);
         }
-        stage_append(a, st, cand, w, e - s, cs);
     }
 }
 
-__device__ __forceinline__ void inc_b_block(const Args& a, Stage* st, int k, int w, int* sh, long long* dedges) {
+// Dirty vertex w handled by a group of GS lanes (GS = kBlock: the whole
+// workgroup, with LDS for the reductions).  Returns via the stage: w itself
+// to the k_inc_b list or, when its count is final and 0, to the candidates.
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* stgb, int k, int w, int lig,
+                                             uint64_t* red, int* shc, long long* dedges) {
+    S* st = static_cast<S*>(a.st);
+    const unsigned* bits = dbits(a, k);
+    const int cs = cset(k);
     const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
     const int lim = s + a.split[w];
-    const int now = a.tent[w], old = a.told[w];
-    const int cs = cset(k);
-    if (threadIdx.x == 0) *dedges += e - s;
-    int c = 0;
-    for (int p = s + (int)threadIdx.x; p < e; p += kBlock) {
-        int x;
-        const bool cand = inc_b_entry(a, k, w, p, lim, now, old, &c, &x);
-        stage_append_lookup(a, st, cand, x, cs);
+    const int old = st[w];
+    const bool cached = (e - s) <= kCache * GS;
+    int xs[kCache], sv[kCache];
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) {
+            const int p = s + lig + j * GS;
+            xs[j] = p < e ? a.colp[p] : w;
+        }
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) sv[j] = st[xs[j]];  // p >= e reads w's own (positive) word
     }
+    // new tentative colour: first window of 64 colours with a free slot
+    int now;
+    for (int base = 1;; base += 64) {
+        uint64_t m = 0;
+        if (cached) {
+#pragma unroll
+            for (int j = 0; j < kCache; ++j) {
+                const unsigned c = (unsigned)(-sv[j] - base);
+                if (c < 64u) m |= 1ull << c;
+            }
+        } else {
+            m = state_window<GS, S>(s + lig, e, base, a.colp, st);
+        }
+        if constexpr (GS == kBlock) {
+            m = group_or<kWave>(m);
+            if (__lane_id() == 0) red[threadIdx.x / kWave] = m;
+            __syncthreads();
+            m = red[0] | red[1] | red[2] | red[3];
+            __syncthreads();
+        } else {
+            m = group_or<GS>(m);
+        }
+        if (~m) {
+            now = base + __builtin_ctzll(~m);
+            break;
+        }
+    }
+    // counters
+    int cnt = 0;
+    bool dlow = false;
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) {
+            const int p = s + lig + j * GS;
+            if (p < e && inc_a_eval(a, bits, k, w, p, lim, now, old, xs[j], sv[j], &cnt, &dlow))
+                stage_append_lookup(a, stg, true, xs[j], cs);
+        }
+    } else {
+        inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
+    }
+    int dl = dlow ? 1 : 0;
+    if constexpr (GS == kBlock) {
+        cnt = group_sum<kWave>(cnt);
+        dl = group_sum<kWave>(dl);
+        if (__lane_id() == 0) {
+            shc[threadIdx.x / kWave] = cnt;
+            shc[4 + threadIdx.x / kWave] = dl;
+        }
+        __syncthreads();
+        cnt = shc[0] + shc[1] + shc[2] + shc[3];
+        dl = shc[4] + shc[5] + shc[6] + shc[7];
+        __syncthreads();
+    } else {
+        cnt = group_sum<GS>(cnt);
+        dl = group_sum<GS>(dl);
+    }
+    bool to_b = false, cand = false;
+    if (lig == 0) {
+        st[w] = (S)now;
+        a.conf[w] = cnt;
+        *dedges += e - s;
+        to_b = dl > 0;
+        cand = !to_b && cnt == 0 && (atomicExch(&a.cflag[w], k) != k);
+    }
+    if (GS == kBlock && threadIdx.x >= kWave) return;
+    stage_append(a, stgb, to_b, w, e - s, kSetB);
+    stage_append(a, stg, cand, w, e - s, cs);
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, Stage* stgb, int k, const int* list, int cnt,
+                                            int local, long long* dedges) {
+    constexpr int CV = kBlock / GS;
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, dedges);
+}
+
+// Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
+// (its list is still intact), so that round k+1 can reuse it.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
+    __shared__ uint64_t red[kBlock / kWave];
+    __shared__ int shc[8];
+    __shared__ Stage stg;
+    __shared__ Stage stgb;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && k - 1 < kMaxLog) {
+        long long nd = 0;
+        for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dlist(k)][b];
+        a.log[kLogW * (k - 1) + 0] = 0;
+        a.log[kLogW * (k - 1) + 1] = 0;
+        a.log[kLogW * (k - 1) + 2] = nd;
+        a.log[kLogW * (k - 1) + 3] = 0;
+    }
+    const ChunkMap m = make_map(a.ctl, dlist(k));
+    int nprev = 0;
+    for (int b = 0; b < kBins; ++b) nprev += a.ctl->cnt[dlist(k - 1)][b];
+    const int clear_blocks = (nprev + kBlock - 1) / kBlock;
+    if ((int)blockIdx.x >= max(m.total, clear_blocks)) return;
+    {
+        // every bit of that bitmap belongs to a previous dirty vertex, so the
+        // words holding them can be zeroed whole
+        unsigned* pbits = dbits(a, k - 1);
+        for (int b = 0; b < kBins; ++b) {
+            const int c = a.ctl->cnt[dlist(k - 1)][b];
+            const int* l = list_ptr(a, dlist(k - 1), b);
+            for (int i = blockIdx.x * kBlock + threadIdx.x; i < c; i += gridDim.x * kBlock) pbits[l[i] >> 5] = 0u;
+        }
+    }
+    stage_init(&stg);
+    stage_init(&stgb);
+    long long dedges = 0;
+#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, &dedges)
+#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, &dedges)
+#define A_AFTER()                                \
+    {                                            \
+        stage_maybe_flush(a, &stg, cset(k));     \
+        stage_maybe_flush(a, &stgb, kSetB);      \
+    }
+    GC_WALK_CHUNKS(a, m, dlist(k), A_GS, A_BLOCK, A_AFTER)
+#undef A_GS
+#undef A_BLOCK
+#undef A_AFTER
+    stage_flush(a, &stg, cset(k));
+    stage_flush(a, &stgb, kSetB);
+    if (k - 1 < kMaxLog) block_add_log(dedges, &a.log[kLogW * (k - 1) + 3]);
+}
+
+// Round k, kernel B: for dirty vertices with preceding dirty neighbours, add
+// those holding the same (final) new colour to the counter.
+template <int STRIDE, typename S>
+__device__ __forceinline__ int inc_b_count(const Args& a, const S* __restrict__ st,
+                                           const unsigned* __restrict__ bits, int w, int start, int lim, int now) {
+    int c = 0;
+    for (int p0 = start; p0 < lim; p0 += 4 * STRIDE) {
+        int x[4];
+        bool d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            x[j] = p < lim ? a.colp[p] : w;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] = (p0 + j * STRIDE < lim) && is_dirty(bits, x[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (d[j]) c += ((int)st[x[j]] == now);
+    }
+    return c;
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_b_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local) {
+    constexpr int CV = kBlock / GS;
+    const S* st = static_cast<const S*>(a.st);
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    bool cand = false;
+    int w = 0, deg = 0;
+    if (idx < cnt) {
+        w = list[idx];
+        const int s = a.row_ptr[w];
+        deg = a.row_ptr[w + 1] - s;
+        const int now = st[w];
+        int c = inc_b_count<GS, S>(a, st, dbits(a, k), w, s + lig, s + a.split[w], now);
+        c = group_sum<GS>(c);
+        if (lig == 0) {
+            const int tot = a.conf[w] + c;
+            a.conf[w] = tot;
+            cand = tot == 0 && (atomicExch(&a.cflag[w], k) != k);
+        }
+    }
+    stage_append(a, stg, cand, w, deg, cset(k));
+}
+
+template <typename S>
+__device__ __forceinline__ void inc_b_block(const Args& a, Stage* stg, int k, int w, int* sh) {
+    const S* st = static_cast<const S*>(a.st);
+    const int s = a.row_ptr[w], deg = a.row_ptr[w + 1] - s;
+    const int now = st[w];
+    int c = inc_b_count<kBlock, S>(a, st, dbits(a, k), w, s + (int)threadIdx.x, s + a.split[w], now);
     c = group_sum<kWave>(c);
     if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -620,58 +865,87 @@ __device__ __forceinline__ void inc_b_block(const Args& a, Stage* st, int k, int
     __syncthreads();
     bool cand = false;
     if (threadIdx.x == 0) {
-        a.conf[w] = tot;
-        cand = (tot == 0) && (atomicExch(&a.cflag[w], k) != k);
+        const int t = a.conf[w] + tot;
+        a.conf[w] = t;
+        cand = t == 0 && (atomicExch(&a.cflag[w], k) != k);
     }
-    if (threadIdx.x < kWave) stage_append(a, st, cand, w, e - s, cs);
+    if (threadIdx.x < kWave) stage_append(a, stg, cand, w, deg, cset(k));
 }
 
+// Also clears the list that round k+1's commits fill (round k-2's dirty list,
+// whose bits k_inc_a of round k-1 cleared).
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_b(Args a, int k) {
     __shared__ int sh[kBlock / kWave];
-    __shared__ Stage st;
-    stage_init(&st);
-    long long dedges = 0;
-    const int cs = cset(k);
-#define B_GS(GS, L, C, LOC) inc_b_chunk<GS>(a, &st, k, L, C, LOC, &dedges)
-#define B_BLOCK(V) inc_b_block(a, &st, k, (V), sh, &dedges)
-#define B_AFTER() stage_maybe_flush(a, &st, cs)
-    GC_FOR_CHUNKS(a, dset(k), B_GS, B_BLOCK, B_AFTER)
+    __shared__ Stage stg;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[dlist(k + 1)][b] = 0;
+    const ChunkMap m = make_map(a.ctl, kSetB);
+    if ((int)blockIdx.x >= m.total) return;
+    stage_init(&stg);
+#define B_GS(GS, L, C, LOC) inc_b_chunk<GS, S>(a, &stg, k, L, C, LOC)
+#define B_BLOCK(V) inc_b_block<S>(a, &stg, k, (V), sh)
+#define B_AFTER() stage_maybe_flush(a, &stg, cset(k))
+    GC_WALK_CHUNKS(a, m, kSetB, B_GS, B_BLOCK, B_AFTER)
 #undef B_GS
 #undef B_BLOCK
 #undef B_AFTER
-    stage_flush(a, &st, cs);
-    if (k - 1 < kMaxLog) block_add_log(dedges, &a.log[kLogW * (k - 1) + 3]);
+    stage_flush(a, &stg, cset(k));
 }
 
-// Dirty mark from a committed vertex v (colour t) to one row entry u: u is
-// uncoloured with tentative colour t, so its tentative colour must move in
-// round k+1.  Returns true for the first mark of u.
-__device__ __forceinline__ bool inc_c_entry(const Args& a, int k, int v, int u, int t) {
-    if (u == v || a.tent[u] != t) return false;  // committed u hold 0 and never match
+// Dirty mark from a committed vertex v (colour t) to a later row entry u
+// (word su): u is uncoloured with tentative colour t, so its tentative
+// colour must move in round k+1.  Returns true for the first mark of u.  A
+// neighbour committed in this same kernel holds a colour different from t
+// (two adjacent vertices with equal tentative colours cannot both have
+// counter 0), so reading its word before or after its commit gives no match.
+__device__ __forceinline__ bool inc_c_eval(const Args& a, unsigned* __restrict__ nbits, int k, int v, int u, int su,
+                                           int t) {
+    if (u == v || su != t) return false;
     if (a.stamp[u] == k + 1) return false;
-    return atomicExch(&a.stamp[u], k + 1) != k + 1;
+    if (atomicExch(&a.stamp[u], k + 1) == k + 1) return false;
+    atomicOr(&nbits[u >> 5], 1u << (u & 31));
+    return true;
 }
 
-template <int GS>
-__device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* st, int k, const int* list, int cnt, int local,
+template <int STRIDE, typename S>
+__device__ __forceinline__ void inc_c_row(const Args& a, Stage* stg, const S* __restrict__ st, int k, int v, int t,
+                                          int start, int e) {
+    unsigned* nbits = dbits(a, k + 1);
+    const int ds = dlist(k + 1);
+    for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
+        int u[4], su[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            u[j] = p < e ? a.colp[p] : v;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) su[j] = st[u[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool dirty = inc_c_eval(a, nbits, k, v, u[j], su[j], t);
+            stage_append_lookup(a, stg, dirty, u[j], ds);
+        }
+    }
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local,
                                             long long* ncom, long long* ndeg) {
     constexpr int CV = kBlock / GS;
+    S* st = static_cast<S*>(a.st);
     const int lig = threadIdx.x & (GS - 1);
     const int idx = local * CV + (int)threadIdx.x / GS;
-    const int ds = dset(k + 1);
     if (idx < cnt) {
         const int v = list[idx];
-        const int t = a.tent[v];
-        if (a.conf[v] == 0 && t != 0) {
+        const int t = st[v];
+        if (a.conf[v] == 0 && t > 0) {
             const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
-            for (int p = s + lig; p < e; p += GS) {
-                const int u = a.colp[p];
-                const bool dirty = inc_c_entry(a, k, v, u, t);
-                stage_append_lookup(a, st, dirty, u, ds);
-            }
+            inc_c_row<GS, S>(a, stg, st, k, v, t, s + a.split[v] + lig, e);
             if (lig == 0) {
                 a.color[v] = t;
-                a.tent[v] = 0;
+                st[v] = (S)(-t);
                 *ncom += 1;
                 *ndeg += e - s;
                 a.ctl->rounds = k;
@@ -680,47 +954,62 @@ __device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* st, int k, con
     }
 }
 
-__device__ __forceinline__ void inc_c_block(const Args& a, Stage* st, int k, int v, long long* ncom,
+template <typename S>
+__device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, int v, long long* ncom,
                                             long long* ndeg) {
-    const int t = a.tent[v];
-    if (a.conf[v] != 0 || t == 0) return;  // block-uniform: nothing writes them in this kernel for v
+    S* st = static_cast<S*>(a.st);
+    const int t = st[v];
+    if (a.conf[v] != 0 || t <= 0) return;  // block-uniform: only this block writes them in this kernel
     const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
-    const int ds = dset(k + 1);
-    for (int p = s + (int)threadIdx.x; p < e; p += kBlock) {
-        const int u = a.colp[p];
-        const bool dirty = inc_c_entry(a, k, v, u, t);
-        stage_append_lookup(a, st, dirty, u, ds);
-    }
-    __syncthreads();  // every thread has read tent[v] before it is cleared
+    inc_c_row<kBlock, S>(a, stg, st, k, v, t, s + a.split[v] + (int)threadIdx.x, e);
+    __syncthreads();  // every thread has read st[v] before it is overwritten
     if (threadIdx.x == 0) {
         a.color[v] = t;
-        a.tent[v] = 0;
+        st[v] = (S)(-t);
         *ncom += 1;
         *ndeg += e - s;
         a.ctl->rounds = k;
     }
 }
 
-// Round k: commit every candidate whose counter is 0, mark its dirty
-// neighbours for round k+1.
+// Round k, kernel C: commit every candidate whose counter is 0, mark its
+// dirty neighbours for round k+1.  Clears the candidate list of round k+1 and
+// the k_inc_b list.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
-    __shared__ Stage st;
-    stage_init(&st);
+    __shared__ Stage stg;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int b = 0; b < 8; ++b) {
+            a.ctl->cnt[cset(k + 1)][b] = 0;
+            a.ctl->cnt[kSetB][b] = 0;
+        }
+    const ChunkMap m = make_map(a.ctl, cset(k));
+    if ((int)blockIdx.x >= m.total) return;
+    stage_init(&stg);
     long long ncom = 0, ndeg = 0;
-    const int ds = dset(k + 1);
-#define C_GS(GS, L, C, LOC) inc_c_chunk<GS>(a, &st, k, L, C, LOC, &ncom, &ndeg)
-#define C_BLOCK(V) inc_c_block(a, &st, k, (V), &ncom, &ndeg)
-#define C_AFTER() stage_maybe_flush(a, &st, ds)
-    GC_FOR_CHUNKS(a, cset(k), C_GS, C_BLOCK, C_AFTER)
+    const int ds = dlist(k + 1);
+#define C_GS(GS, L, C, LOC) inc_c_chunk<GS, S>(a, &stg, k, L, C, LOC, &ncom, &ndeg)
+#define C_BLOCK(V) inc_c_block<S>(a, &stg, k, (V), &ncom, &ndeg)
+#define C_AFTER() stage_maybe_flush(a, &stg, ds)
+    GC_WALK_CHUNKS(a, m, cset(k), C_GS, C_BLOCK, C_AFTER)
 #undef C_GS
 #undef C_BLOCK
 #undef C_AFTER
-    stage_flush(a, &st, ds);
+    stage_flush(a, &stg, ds);
     block_add_log(ncom, (long long*)&a.ctl->committed);
     if (k - 1 < kMaxLog) {
         block_add_log(ncom, &a.log[kLogW * (k - 1)]);
         block_add_log(ndeg, &a.log[kLogW * (k - 1) + 1]);
     }
+}
+
+// Largest row length (the colour bound Delta + 1 picks the state width).
+__global__ __launch_bounds__(kBlock) void k_maxdeg(int n, const int* __restrict__ row_ptr, Ctl* ctl) {
+    int mx = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock)
+        mx = max(mx, row_ptr[v + 1] - row_ptr[v]);
+    for (int o = kWave / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+    if (__lane_id() == 0 && mx) atomicMax(&ctl->maxdeg, mx);
 }
 
 // ---------------------------------------------------------------------------
@@ -972,7 +1261,7 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, colp, total;
+    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, dbits, colp, total;
 };
 
 Layout layout(int32_t n, int64_t nnz) {
@@ -988,6 +1277,7 @@ Layout layout(int32_t n, int64_t nnz) {
     L.cflag = off; off += align_up(vn);
     L.split = off; off += align_up(vn);
     L.lists = off; off += align_up(vn * kSets * kBins);
+    L.dbits = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.colp = off;  off += align_up(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     L.total = off;
     return L;
@@ -1149,18 +1439,19 @@ int run_plain(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hi
     }
 }
 
+template <typename S>
 int run_incremental(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st) {
-    GC_CHECK(L(kProfIncC, [&] { k_inc_c<<<grid, kBlock, 0, st>>>(a, 1); }));
+    GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid, kBlock, 0, st>>>(a, 1); }));
     int k = 2;
     int batch = 4;
     for (;;) {
         for (int j = 0; j < batch; ++j, ++k) {
-            GC_CHECK(L(kProfIncA, [&] { k_inc_a<<<grid, kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncB, [&] { k_inc_b<<<grid, kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncC, [&] { k_inc_c<<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncB, [&] { k_inc_b<S><<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid, kBlock, 0, st>>>(a, k); }));
         }
         // dirty list of the next round k: empty exactly when every vertex is committed
-        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dset(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dlist(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
         GC_CHECK(hipStreamSynchronize(st));
         if (sum_counts(host) == 0) break;
         if (k > n + 64) return GCOLOR_EROUNDS;
@@ -1206,11 +1497,15 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     a.split = reinterpret_cast<int*>(base + Lw.split);
     a.color = colors;
     a.tent = reinterpret_cast<int*>(base + Lw.tent);
-    a.told = reinterpret_cast<int*>(base + Lw.told);
+    // the incremental engine's state words share the plain engine's slots
+    a.st = base + Lw.tent;
+    a.stold = base + Lw.told;
     a.conf = reinterpret_cast<int*>(base + Lw.conf);
     a.stamp = reinterpret_cast<int*>(base + Lw.stamp);
     a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
     a.lists = reinterpret_cast<int*>(base + Lw.lists);
+    a.dbits = reinterpret_cast<unsigned*>(base + Lw.dbits);
+    a.nwords = (int)(((int64_t)n + 31) / 32);
     a.ctl = ctl;
     a.log = log;
     a.cfg = current_bins();
@@ -1237,9 +1532,20 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         }
         rc = run_plain(a, n, grid, L, host, st);
     } else {
-        k_inc_seed<<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+        // colours are at most max degree + 1: 16-bit state words when that fits
+        k_maxdeg<<<vgrid, kBlock, 0, st>>>(n, row_ptr, ctl);
         GC_CHECK(hipGetLastError());
-        rc = run_incremental(a, n, grid, L, host, st);
+        GC_CHECK(hipMemcpyAsync(host, &ctl->maxdeg, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        if (host[0] + 1 <= 32767) {
+            k_inc_seed<int16_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+            GC_CHECK(hipGetLastError());
+            rc = run_incremental<int16_t>(a, n, grid, L, host, st);
+        } else {
+            k_inc_seed<int32_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+            GC_CHECK(hipGetLastError());
+            rc = run_incremental<int32_t>(a, n, grid, L, host, st);
+        }
     }
     if (rc) return rc;
 

@@ -86,7 +86,7 @@ def test_complete_graphs_many_windows(n):
     assert st.num_colors == n and st.rounds == n
 
 
-@pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (70000, 123)])
+@pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (32767, 5), (32768, 5), (70000, 123)])
 def test_star_hubs(n, center):
     """A centre of degree up to 70k runs on the workgroup-per-vertex bin."""
     check(graphgen.star(n, center), label="star")
