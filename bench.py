@@ -70,7 +70,53 @@ def load_traffic(workload, order, kernel, launches):
     return k.get("hbm_bytes_per_launch")
 
 
+def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings):
+    """Write profiles/traffic_<workload>_<order>.json from two rocprofv3 --pmc
+    runs of this script (FETCH_SIZE, then WRITE_SIZE, both with
+    --copy-calibration).  Each counter is scaled by what it reads for the
+    1 GiB device copy of the calibration (bytes known), per kernel launch."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        tot, disp, copy = {}, {}, None
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            if "copyBuffer" in name and int(r["Grid_Size"]) == 131072:
+                copy = val  # the 1 GiB calibration copy
+                continue
+            m = re.search(r"k_(inc_[abc]|phase[12])", name)
+            if m:
+                key = m.group(1)
+                tot[key] = tot.get(key, 0.0) + val
+                disp[key] = disp.get(key, 0) + 1
+        return tot, disp, copy
+
+    ft, fd, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    wt, wd, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    gib_kib = 1024.0 * 1024.0
+    fscale = gib_kib / fcopy if fcopy else None   # true read bytes / counted
+    wscale = gib_kib / wcopy if wcopy else None
+    out = {"kernel_source_sha256": kernel_source_digest(), "workload": workload, "order": order,
+           "copy_calibration_kib": {"FETCH_SIZE": fcopy, "WRITE_SIZE": wcopy, "true_kib": gib_kib},
+           "scale": {"FETCH_SIZE": fscale, "WRITE_SIZE": wscale}, "kernels": {}}
+    for k in sorted(ft):
+        rd = ft[k] / fd[k] * 1024.0 * fscale
+        wr = wt.get(k, 0.0) / max(wd.get(k, 1), 1) * 1024.0 * wscale
+        out["kernels"][k] = {"launches_counted": fd[k], "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+                             "hbm_bytes_per_launch": rd + wr}
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
+    json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+    print(path)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--derive-traffic":
+        # --derive-traffic FETCH_CSV WRITE_CSV WORKLOAD ORDER
+        derive_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], None)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -202,6 +248,10 @@ def main():
         launches = kern[dom]["launches"]
         achieved = (algo[dom] / max(launches, 1)) / (kern[dom]["avg_us"] * 1e-6) / 1e9
         traffic = load_traffic(args.workload, args.order, dom, launches)
+        if traffic is not None:
+            traffic = {"hbm_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch":
+                       round(algo[dom] / max(launches, 1)),
+                       "GB_per_s": round(traffic / (kern[dom]["avg_us"] * 1e-6) / 1e9, 1)}
         roofline = {
             "kernel": dom,
             "bound": "hbm",

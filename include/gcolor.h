@@ -139,6 +139,36 @@ int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
 int gcolor_profile(int32_t enable);
 int gcolor_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
 
+/*
+ * Batched colouring of many independent graphs in one persistent launch
+ * (each graph is coloured exactly as color_graph colours it alone).
+ *   vtx_off  int64[G+1]  vertex offsets: graph g owns vertices
+ *                        [vtx_off[g], vtx_off[g+1]) of colors_out / priority;
+ *   edge_off int64[G+1]  entry offsets of each graph in col_idx;
+ *   row_ptr  int32[V+G]  each graph's own n_g+1 row offsets (local, starting
+ *                        at 0), concatenated: graph g's at vtx_off[g] + g;
+ *   col_idx  int32[nnz]  local neighbour ids (0 .. n_g-1), symmetric per graph;
+ *                        rows sorted ascending unless priority is given;
+ *   priority uint32[V] or NULL (precedence within each graph, ties by id);
+ *   total_vertices = V = vtx_off[G], total_nnz = edge_off[G] (the caller knows
+ *   them; they size the workspace, no device value is read back).
+ * workspace: device memory of gcolor_batch_workspace_bytes(G, V, nnz) bytes.
+ * ticks (int64[2G], optional): per graph, wall-clock ticks (rate from
+ * gcolor_wall_clock_khz) when its workgroup started and finished it.
+ * rounds (int32[G], optional): rounds each graph took.
+ * Fully asynchronous on `stream`: no host synchronisation, no allocation, so
+ * the call may be captured into a HIP graph.  Malformed input is not
+ * detected (validate with color_graph_ex per graph when in doubt).
+ */
+size_t gcolor_batch_workspace_bytes(int32_t num_graphs, int64_t total_vertices, int64_t total_nnz);
+int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_nnz, const int64_t* vtx_off,
+                      const int64_t* edge_off, const int32_t* row_ptr, const int32_t* col_idx,
+                      const uint32_t* priority, int32_t* colors_out, void* workspace, size_t ws_bytes,
+                      int64_t* ticks, int32_t* rounds, gcolor_stream_t stream);
+
+/* Rate of the device wall clock used by the batch ticks, in kHz. */
+int gcolor_wall_clock_khz(int32_t* khz);
+
 /* Human-readable name of a return code. */
 const char* gcolor_strerror(int code);
 

@@ -27,4 +27,7 @@ from ._binding import (  # noqa: F401
     profile_read,
     raw_library,
     set_tuning,
+    batch_workspace_bytes,
+    color_graph_batch,
+    wall_clock_khz,
 )

@@ -76,6 +76,13 @@ def _load():
     lib.gcolor_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]
     lib.gcolor_profile_read.restype = ctypes.c_int
+    lib.gcolor_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+    lib.gcolor_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.color_graph_batch.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp,
+                                      vp, ctypes.c_size_t, vp, vp, vp]
+    lib.color_graph_batch.restype = ctypes.c_int
+    lib.gcolor_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.gcolor_wall_clock_khz.restype = ctypes.c_int
     return lib
 
 
@@ -226,3 +233,52 @@ def profile_read(kernel: int):
 def raw_library():
     """The loaded ctypes library (for ABI-level tests)."""
     return _lib
+
+
+def batch_workspace_bytes(num_graphs: int, total_vertices: int, total_nnz: int) -> int:
+    return int(_lib.gcolor_batch_workspace_bytes(int(num_graphs), int(total_vertices), int(total_nnz)))
+
+
+def wall_clock_khz() -> int:
+    khz = ctypes.c_int32()
+    rc = _lib.gcolor_wall_clock_khz(ctypes.byref(khz))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_wall_clock_khz")
+    return int(khz.value)
+
+
+def color_graph_batch(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.Tensor, col_idx: torch.Tensor,
+                      total_vertices: int, total_nnz: int, priority: Optional[torch.Tensor] = None,
+                      colors_out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                      ticks: Optional[torch.Tensor] = None, rounds: Optional[torch.Tensor] = None, stream=None):
+    """Colour G independent graphs in one launch (asynchronous, capturable).
+
+    vtx_off/edge_off: int64[G+1]; row_ptr: int32[V+G] (each graph's local
+    offsets, concatenated); col_idx: int32[nnz] local ids.  total_vertices and
+    total_nnz are V and nnz (passed in so that nothing is read back).
+    Returns colors_out (int32[V]).
+    """
+    G = vtx_off.numel() - 1
+    if G < 0:
+        raise ValueError("vtx_off must have G+1 entries")
+    i64 = (torch.int64,)
+    vo = _dev_ptr(vtx_off, "vtx_off", i64, G + 1)
+    eo = _dev_ptr(edge_off, "edge_off", i64, G + 1)
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32, int(total_vertices) + G)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    pr = _dev_ptr(priority, "priority", _KEY, int(total_vertices))
+    if colors_out is None:
+        colors_out = torch.empty(int(total_vertices), dtype=torch.int32, device=row_ptr.device)
+    co = _dev_ptr(colors_out, "colors_out", _I32, int(total_vertices))
+    if workspace is None:
+        workspace = torch.empty(batch_workspace_bytes(G, total_vertices, total_nnz), dtype=torch.uint8,
+                                device=row_ptr.device)
+    ws = _dev_ptr(workspace, "workspace", (torch.uint8, torch.int8, torch.int32, torch.int64))
+    tk = _dev_ptr(ticks, "ticks", i64, 2 * G)
+    rd = _dev_ptr(rounds, "rounds", _I32, G)
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.color_graph_batch(G, int(total_vertices), int(total_nnz), vo, eo, rp, ci, pr, co, ws,
+                                    workspace.numel() * workspace.element_size(), tk, rd, _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "color_graph_batch")
+    return colors_out
