@@ -169,6 +169,73 @@ int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_
 /* Rate of the device wall clock used by the batch ticks, in kHz. */
 int gcolor_wall_clock_khz(int32_t* khz);
 
+/*
+ * Learned ordering (a small MLP predicts each vertex's normalised position in
+ * the smallest-last order; its scores become priority keys).
+ *
+ * Model: 8 features -> 64 -> 64 -> 1, ReLU.  Parameters live in one FP32
+ * array `master` of GCOLOR_MLP_NPARAM floats laid out as below (W row-major,
+ * row = output unit); the forward pass uses BF16 copies `wbf` (uint16 bits,
+ * same layout; only the W entries are read) and accumulates in FP32.
+ * `norm` holds 16 floats: per-feature mean and standard deviation of
+ * log1p(feature) over the training vertices; x = (log1p(f) - mean) / std.
+ */
+#define GCOLOR_MLP_FEATURES 8
+#define GCOLOR_MLP_HIDDEN 64
+#define GCOLOR_MLP_W1 0     /* [64][8] */
+#define GCOLOR_MLP_B1 512   /* [64] */
+#define GCOLOR_MLP_W2 576   /* [64][64] */
+#define GCOLOR_MLP_B2 4672  /* [64] */
+#define GCOLOR_MLP_W3 4736  /* [64] */
+#define GCOLOR_MLP_B3 4800  /* [1] */
+#define GCOLOR_MLP_NPARAM 4801
+
+/*
+ * Raw features, float[n][8] (device): degree, log2(1 + degree), min / mean /
+ * max neighbour degree, two-hop paths (sum of neighbour degree - 1), a
+ * triangle estimate from 8 hashed wedges (closed fraction times
+ * degree (degree - 1) / 2; wedge choices are splitmix64 of (seed, vertex,
+ * sample)), and the h-index of the neighbour degrees (a core-number
+ * estimate).  Rows must be sorted ascending.
+ */
+int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
+                    gcolor_stream_t stream);
+
+/* Adds sum and sum of squares of log1p(feature) per feature (double[16],
+ * device, caller zeroes it) over n vertices. */
+int gcolor_feature_stats(int64_t n, const float* feat, double* acc, gcolor_stream_t stream);
+
+/* score[v] for n vertices (all pointers device). */
+int gcolor_mlp_forward(int64_t n, const float* feat, const float* master, const uint16_t* wbf, const float* norm,
+                       float* score, gcolor_stream_t stream);
+
+/*
+ * Gradient of the mean squared error over a minibatch: vertices idx[0..batch)
+ * of feat, targets target[v].  grad (float[NPARAM + 1], device) receives the
+ * gradient and, last, the loss; partial is device scratch of
+ * gcolor_mlp_partial_floats(batch) floats.
+ */
+size_t gcolor_mlp_partial_floats(int32_t batch);
+int gcolor_mlp_grad(int32_t batch, const int32_t* idx, const float* feat, const float* target, const float* master,
+                    const uint16_t* wbf, const float* norm, float* partial, float* grad, gcolor_stream_t stream);
+
+/* Adam step (step >= 1) on master, refreshing wbf; mom/vel are NPARAM floats. */
+int gcolor_mlp_adam(float* master, uint16_t* wbf, float* mom, float* vel, const float* grad, float lr, float beta1,
+                    float beta2, float eps, int32_t step, gcolor_stream_t stream);
+
+/* wbf = BF16(master), round to nearest even. */
+int gcolor_mlp_refresh_bf16(const float* master, uint16_t* wbf, gcolor_stream_t stream);
+
+/* Order-preserving float -> uint32 keys; *bad (device int) is set to 1 when
+ * a score is NaN (caller zeroes it). */
+int gcolor_scores_to_keys(int64_t n, const float* score, uint32_t* keys, int32_t* bad, gcolor_stream_t stream);
+
+/* Exact smallest-last order on the host (host pointers): rank[v] = position
+ * in the colouring order (the reverse of the removal order; each removal
+ * takes a minimum-degree vertex, the smallest id among them). */
+int gcolor_smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* rank,
+                              int32_t* degeneracy);
+
 /* Human-readable name of a return code. */
 const char* gcolor_strerror(int code);
 

@@ -83,6 +83,20 @@ def _load():
     lib.color_graph_batch.restype = ctypes.c_int
     lib.gcolor_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.gcolor_wall_clock_khz.restype = ctypes.c_int
+    lib.gcolor_features.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_uint64, vp, vp]
+    lib.gcolor_feature_stats.argtypes = [ctypes.c_int64, vp, vp, vp]
+    lib.gcolor_mlp_forward.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.gcolor_mlp_partial_floats.argtypes = [ctypes.c_int32]
+    lib.gcolor_mlp_partial_floats.restype = ctypes.c_size_t
+    lib.gcolor_mlp_grad.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.gcolor_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_int32, vp]
+    lib.gcolor_mlp_refresh_bf16.argtypes = [vp, vp, vp]
+    lib.gcolor_scores_to_keys.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
+    lib.gcolor_smallest_last_host.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
+    for f in ("gcolor_features", "gcolor_feature_stats", "gcolor_mlp_forward", "gcolor_mlp_grad", "gcolor_mlp_adam",
+              "gcolor_mlp_refresh_bf16", "gcolor_scores_to_keys", "gcolor_smallest_last_host"):
+        getattr(lib, f).restype = ctypes.c_int
     return lib
 
 

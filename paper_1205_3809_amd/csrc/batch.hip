@@ -98,6 +98,18 @@ __device__ __forceinline__ int gsum(int x) {
 
 __device__ __forceinline__ bool dirty_bit(const unsigned* b, int x) { return (b[x >> 5] >> (x & 31)) & 1u; }
 
+// One workgroup owns all of a graph's working data, so its atomics need only
+// workgroup scope (shorter round trips than device-scope ones).
+__device__ __forceinline__ int wg_add(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int wg_exch(int* p, int v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned wg_or(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Per-workgroup list lengths live in LDS: cnt[0..2] dirty, [3..4] candidates, [5] second pass.
 __device__ __forceinline__ void push(const GView& g, int* cnt, int list, int v) {
     const int slot = atomicAdd(&cnt[list], 1);
@@ -118,11 +130,11 @@ __device__ __forceinline__ bool eval_dirty(const GView& g, const unsigned* bits,
     if (x == w || (sx != now && sx != old)) return false;
     if (dirty_bit(bits, x)) return false;
     if (sx == now) {
-        atomicAdd(&g.conf[x], 1);
+        wg_add(&g.conf[x], 1);
         return false;
     }
-    if (atomicSub(&g.conf[x], 1) != 1) return false;
-    return atomicExch(&g.cflag[x], k) != k;
+    if (wg_add(&g.conf[x], -1) != 1) return false;
+    return wg_exch(&g.cflag[x], k) != k;
 }
 
 // Phase A of round k for dirty vertex w (group of kG lanes).
@@ -184,7 +196,7 @@ __device__ void phase_a(const GView& g, int* cnt, int k, int w, int lig) {
         g.st[w] = now;
         g.conf[w] = c;
         if (d > 0) push(g, cnt, 5, w);
-        else if (c == 0 && atomicExch(&g.cflag[w], k) != k) push(g, cnt, cl(k), w);
+        else if (c == 0 && wg_exch(&g.cflag[w], k) != k) push(g, cnt, cl(k), w);
     }
 }
 
@@ -204,7 +216,7 @@ __device__ void phase_b(const GView& g, int* cnt, int k, int w, int lig) {
     if (lig == 0) {
         const int t = g.conf[w] + c;
         g.conf[w] = t;
-        if (t == 0 && atomicExch(&g.cflag[w], k) != k) push(g, cnt, cl(k), w);
+        if (t == 0 && wg_exch(&g.cflag[w], k) != k) push(g, cnt, cl(k), w);
     }
 }
 
@@ -219,8 +231,8 @@ __device__ void phase_c(const GView& g, int* cnt, int k, int v, int lig) {
         const int u = g.col[p];
         if (u == v || g.st[u] != t) continue;
         if (g.stamp[u] == k + 1) continue;
-        if (atomicExch(&g.stamp[u], k + 1) == k + 1) continue;
-        atomicOr(&nbits[u >> 5], 1u << (u & 31));
+        if (wg_exch(&g.stamp[u], k + 1) == k + 1) continue;
+        wg_or(&nbits[u >> 5], 1u << (u & 31));
         push(g, cnt, dl(k + 1), u);
     }
     if (lig == 0) {

@@ -1,0 +1,579 @@
+// Learned vertex ordering for the speculative colouring.
+//
+// Greedy first-fit uses a number of colours that depends on the vertex order;
+// smallest-last order (Matula and Beck) is a good but sequential order.  A
+// small MLP predicts, from local degree features, each vertex's normalised
+// position in the smallest-last order; its scores become priority keys
+// (lower score = coloured earlier, ties by vertex id) for color_graph.
+//
+// Kernels:
+//   k_features     8 raw features per vertex (one group of lanes per vertex)
+//   k_feat_stats   per-feature sum and sum of squares of log1p(feature)
+//   k_mlp_forward  score per vertex: x = (log1p(f) - mean) / std,
+//                  y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, weights in BF16
+//                  (stored as bf16 bits), FP32 accumulation
+//   k_mlp_backward per-workgroup partial gradients of the mean squared error
+//                  over a minibatch (same BF16 weights in the forward part)
+//   k_grad_reduce  sums the partials
+//   k_adam         Adam update of the FP32 master weights, refresh of the
+//                  BF16 copies
+//   k_score_keys   order-preserving float -> uint32 map
+// Host: exact smallest-last ranks (the training targets), bucket queue with
+// per-degree min-heaps so ties go to the smallest id.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <queue>
+#include <thread>
+#include <vector>
+
+#include "gcolor.h"
+
+namespace {
+
+constexpr int kF = GCOLOR_MLP_FEATURES;  // 8
+constexpr int kH = GCOLOR_MLP_HIDDEN;    // 64
+constexpr int kNP = GCOLOR_MLP_NPARAM;   // 4801
+constexpr int kPW1 = GCOLOR_MLP_W1, kPB1 = GCOLOR_MLP_B1, kPW2 = GCOLOR_MLP_W2, kPB2 = GCOLOR_MLP_B2;
+constexpr int kPW3 = GCOLOR_MLP_W3, kPB3 = GCOLOR_MLP_B3;
+constexpr int kWedges = 8;
+
+// ---------------------------------------------------------------------------
+// Features
+// ---------------------------------------------------------------------------
+
+// splitmix64 output mix (Steele, Lea, Flood 2014): wedge choices are a pure
+// function of (seed, vertex, sample index).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ bool has_edge(const int* __restrict__ row_ptr, const int* __restrict__ col, int a, int b) {
+    int lo = row_ptr[a], hi = row_ptr[a + 1];
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        const int c = col[mid];
+        if (c < b) lo = mid + 1;
+        else if (c > b) hi = mid;
+        else return true;
+    }
+    return false;
+}
+
+// One vertex per group of GS lanes.  Features (float, raw):
+//  0 degree            1 log2(1 + degree)
+//  2 min neighbour degree   3 mean neighbour degree   4 max neighbour degree
+//  5 two-hop paths: sum over neighbours of (degree - 1)
+//  6 triangle estimate: closed fraction of 8 hashed wedges * deg (deg-1) / 2
+//  7 core estimate: h-index of the neighbour degrees
+template <int GS>
+__device__ void features_vertex(int v, int lig, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                uint64_t seed, float* __restrict__ out) {
+    const int s = row_ptr[v], e = row_ptr[v + 1];
+    const int d = e - s;
+    int mn = 0x7fffffff, mx = 0;
+    long long sum = 0;
+    for (int p = s + lig; p < e; p += GS) {
+        const int w = col[p];
+        const int dw = row_ptr[w + 1] - row_ptr[w];
+        mn = min(mn, dw);
+        mx = max(mx, dw);
+        sum += dw;
+    }
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, GS));
+        mx = max(mx, __shfl_xor(mx, o, GS));
+        sum += __shfl_xor(sum, o, GS);
+    }
+    // h-index: largest h with at least h neighbours of degree >= h (binary search)
+    int lo = 0, hi = d;
+    while (lo < hi) {
+        const int h = (lo + hi + 1) >> 1;
+        int c = 0;
+        for (int p = s + lig; p < e; p += GS) c += (row_ptr[col[p] + 1] - row_ptr[col[p]]) >= h;
+#pragma unroll
+        for (int o = GS / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, GS);
+        if (c >= h) lo = h;
+        else hi = h - 1;
+    }
+    // wedges: lane i < kWedges samples wedge i
+    int closed = 0;
+    if (d >= 2) {
+        for (int i = lig; i < kWedges; i += GS) {
+            const uint64_t h = mix64(seed * 0x9E3779B97F4A7C15ULL + mix64((uint64_t)v * 8ULL + (uint64_t)i + 1ULL));
+            const int a = (int)((h & 0xffffffffULL) % (uint64_t)d);
+            int b = (int)((h >> 32) % (uint64_t)(d - 1));
+            if (b >= a) b += 1;
+            closed += has_edge(row_ptr, col, col[s + a], col[s + b]) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) closed += __shfl_xor(closed, o, GS);
+    if (lig == 0) {
+        float* f = out + (size_t)v * kF;
+        f[0] = (float)d;
+        f[1] = log2f(1.0f + (float)d);
+        f[2] = d ? (float)mn : 0.0f;
+        f[3] = d ? (float)((double)sum / (double)d) : 0.0f;
+        f[4] = (float)mx;
+        f[5] = (float)(sum - d);
+        f[6] = d >= 2 ? (float)((double)closed / kWedges * 0.5 * (double)d * (double)(d - 1)) : 0.0f;
+        f[7] = (float)lo;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_features(int n, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col, uint64_t seed,
+                                                  float* __restrict__ out) {
+    // 8 lanes per vertex covers the sampled wedges in one pass
+    constexpr int GS = 8;
+    const int groups = gridDim.x * (256 / GS);
+    const int lig = threadIdx.x & (GS - 1);
+    for (int v = blockIdx.x * (256 / GS) + threadIdx.x / GS; v < n; v += groups)
+        features_vertex<GS>(v, lig, row_ptr, col, seed, out);
+}
+
+// Per-feature sum and sum of squares of log1p(feature), in double.
+__global__ __launch_bounds__(256) void k_feat_stats(int64_t n, const float* __restrict__ feat,
+                                                    double* __restrict__ acc /*[2*kF]*/) {
+    double s[kF], q[kF];
+#pragma unroll
+    for (int f = 0; f < kF; ++f) s[f] = q[f] = 0.0;
+    for (int64_t v = blockIdx.x * 256LL + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int f = 0; f < kF; ++f) {
+            const double x = log1p((double)feat[v * kF + f]);
+            s[f] += x;
+            q[f] += x * x;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < kF; ++f) {
+        for (int o = 32; o > 0; o >>= 1) {
+            s[f] += __shfl_xor(s[f], o);
+            q[f] += __shfl_xor(q[f], o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&acc[f], s[f]);
+            atomicAdd(&acc[kF + f], q[f]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MLP
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Round to nearest even.
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Weights the forward pass uses: BF16 copies of W1, W2, W3 widened to FP32
+// in LDS; biases FP32; input normalisation (mean, 1/std).
+struct MlpLds {
+    float w1[kH * kF];
+    float w2[kH * kH];
+    float w3[kH];
+    float b1[kH];
+    float b2[kH];
+    float b3;
+    float mean[kF];
+    float istd[kF];
+};
+
+__device__ void load_mlp(MlpLds* m, const float* __restrict__ master, const uint16_t* __restrict__ wbf,
+                         const float* __restrict__ norm) {
+    for (int i = threadIdx.x; i < kH * kF; i += blockDim.x) m->w1[i] = bf16_to_f32(wbf[kPW1 + i]);
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) m->w2[i] = bf16_to_f32(wbf[kPW2 + i]);
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        m->w3[i] = bf16_to_f32(wbf[kPW3 + i]);
+        m->b1[i] = master[kPB1 + i];
+        m->b2[i] = master[kPB2 + i];
+    }
+    if (threadIdx.x < kF) {
+        m->mean[threadIdx.x] = norm[threadIdx.x];
+        m->istd[threadIdx.x] = 1.0f / norm[kF + threadIdx.x];
+    }
+    if (threadIdx.x == 0) m->b3 = master[kPB3];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void normalise(const MlpLds* m, const float* __restrict__ raw, float* x) {
+#pragma unroll
+    for (int f = 0; f < kF; ++f) x[f] = (log1pf(raw[f]) - m->mean[f]) * m->istd[f];
+}
+
+// One vertex per thread.
+__global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, const float* __restrict__ feat,
+                                                     const float* __restrict__ master,
+                                                     const uint16_t* __restrict__ wbf,
+                                                     const float* __restrict__ norm, float* __restrict__ score) {
+    __shared__ MlpLds m;
+    load_mlp(&m, master, wbf, norm);
+    for (int64_t v = blockIdx.x * 256LL + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        float x[kF], a1[kH];
+        normalise(&m, feat + v * kF, x);
+#pragma unroll
+        for (int i = 0; i < kH; ++i) {
+            float z = m.b1[i];
+#pragma unroll
+            for (int f = 0; f < kF; ++f) z = fmaf(m.w1[i * kF + f], x[f], z);
+            a1[i] = fmaxf(z, 0.0f);
+        }
+        float y = m.b3;
+#pragma unroll 1
+        for (int j = 0; j < kH; ++j) {
+            float z = m.b2[j];
+#pragma unroll
+            for (int i = 0; i < kH; ++i) z = fmaf(m.w2[j * kH + i], a1[i], z);
+            y = fmaf(m.w3[j], fmaxf(z, 0.0f), y);
+        }
+        score[v] = y;
+    }
+}
+
+// Backward over a minibatch of vertices idx[0..B): per workgroup, tiles of
+// 32 vertices, 8 threads per vertex for the per-vertex passes; gradient sums
+// over the workgroup's vertices kept in registers, written as one partial
+// row per workgroup.  Loss = mean over the minibatch of (y - target)^2.
+constexpr int kTile = 32;
+constexpr int kTpv = 256 / kTile;  // threads per vertex
+constexpr int kUpt = kH / kTpv;    // hidden units per thread
+
+struct BwdLds {
+    MlpLds m;
+    float x[kTile][kF];
+    float a1[kTile][kH];
+    float a2[kTile][kH];
+    float dz2[kTile][kH];
+    float dz1[kTile][kH];
+    float dy[kTile];
+    float lsum[256];
+};
+
+__global__ __launch_bounds__(256) void k_mlp_backward(int B, const int* __restrict__ idx, const float* __restrict__ feat,
+                                                      const float* __restrict__ target,
+                                                      const float* __restrict__ master,
+                                                      const uint16_t* __restrict__ wbf,
+                                                      const float* __restrict__ norm, float* __restrict__ partial,
+                                                      int tiles_per_block) {
+    __shared__ BwdLds L;
+    load_mlp(&L.m, master, wbf, norm);
+    const int t = threadIdx.x;
+    const int tv = t / kTpv, tq = t % kTpv;  // vertex slot and unit slice of the per-vertex passes
+    // gradient entries owned by this thread, summed over the block's tiles:
+    //  dW2 row j2, columns i2 .. i2+15; dW1 entries 2t, 2t+1; unit t < 64 of
+    //  db1, db2, dW3; db3 and the loss at thread 0
+    float gw2[16], gw1[2] = {0.f, 0.f}, gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, loss = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) gw2[i] = 0.f;
+    const int j2 = t / 4, i2 = 16 * (t % 4);
+    const float invB = 1.0f / (float)B;
+    for (int tile = 0; tile < tiles_per_block; ++tile) {
+        const int base = (blockIdx.x * tiles_per_block + tile) * kTile;
+        if (base >= B) break;  // uniform over the block
+        const int slot = base + tv;
+        const bool live = slot < B;
+        const int v = live ? idx[slot] : 0;
+        if (tq == 0) {
+            float x[kF];
+            if (live) normalise(&L.m, feat + (int64_t)v * kF, x);
+#pragma unroll
+            for (int f = 0; f < kF; ++f) L.x[tv][f] = live ? x[f] : 0.0f;
+        }
+        __syncthreads();
+        // layer 1, this thread's units
+#pragma unroll 1
+        for (int u = 0; u < kUpt; ++u) {
+            const int i = tq * kUpt + u;
+            float z = L.m.b1[i];
+#pragma unroll
+            for (int f = 0; f < kF; ++f) z = fmaf(L.m.w1[i * kF + f], L.x[tv][f], z);
+            L.a1[tv][i] = fmaxf(z, 0.0f);
+        }
+        __syncthreads();
+        // layer 2 and this thread's share of the output
+        float yp = 0.f;
+#pragma unroll 1
+        for (int u = 0; u < kUpt; ++u) {
+            const int j = tq * kUpt + u;
+            float z = L.m.b2[j];
+#pragma unroll 8
+            for (int i = 0; i < kH; ++i) z = fmaf(L.m.w2[j * kH + i], L.a1[tv][i], z);
+            const float a = fmaxf(z, 0.0f);
+            L.a2[tv][j] = a;
+            yp = fmaf(L.m.w3[j], a, yp);
+        }
+#pragma unroll
+        for (int o = kTpv / 2; o > 0; o >>= 1) yp += __shfl_xor(yp, o, kTpv);
+        if (tq == 0) {
+            const float r = live ? yp + L.m.b3 - target[v] : 0.0f;
+            L.dy[tv] = 2.0f * r * invB;
+            loss += r * r * invB;
+        }
+        __syncthreads();
+        // dL/dz2 = dy * W3 on the active units
+#pragma unroll 1
+        for (int u = 0; u < kUpt; ++u) {
+            const int j = tq * kUpt + u;
+            L.dz2[tv][j] = L.a2[tv][j] > 0.0f ? L.dy[tv] * L.m.w3[j] : 0.0f;
+        }
+        __syncthreads();
+        // dL/dz1 = (W2^T dz2) on the active units
+#pragma unroll 1
+        for (int u = 0; u < kUpt; ++u) {
+            const int i = tq * kUpt + u;
+            float g = 0.f;
+#pragma unroll 8
+            for (int j = 0; j < kH; ++j) g = fmaf(L.m.w2[j * kH + i], L.dz2[tv][j], g);
+            L.dz1[tv][i] = L.a1[tv][i] > 0.0f ? g : 0.0f;
+        }
+        __syncthreads();
+        // sums over the tile's vertices
+#pragma unroll 2
+        for (int b = 0; b < kTile; ++b) {
+            const float dz = L.dz2[b][j2];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) gw2[i] = fmaf(dz, L.a1[b][i2 + i], gw2[i]);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = 2 * t + r, i = e / kF, f = e % kF;
+            float g = 0.f;
+            for (int b = 0; b < kTile; ++b) g = fmaf(L.dz1[b][i], L.x[b][f], g);
+            gw1[r] += g;
+        }
+        if (t < kH) {
+            for (int b = 0; b < kTile; ++b) {
+                gb1 += L.dz1[b][t];
+                gb2 += L.dz2[b][t];
+                gw3 = fmaf(L.a2[b][t], L.dy[b], gw3);
+            }
+        }
+        if (t == 0)
+            for (int b = 0; b < kTile; ++b) gb3 += L.dy[b];
+        __syncthreads();
+    }
+    // one partial row per block: kNP gradients, then the loss
+    float* row = partial + (size_t)blockIdx.x * (kNP + 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) row[kPW2 + j2 * kH + i2 + i] = gw2[i];
+    row[kPW1 + 2 * t] = gw1[0];
+    row[kPW1 + 2 * t + 1] = gw1[1];
+    if (t < kH) {
+        row[kPB1 + t] = gb1;
+        row[kPB2 + t] = gb2;
+        row[kPW3 + t] = gw3;
+    }
+    L.lsum[t] = loss;
+    __syncthreads();
+    if (t == 0) {
+        float s = 0.f;
+        for (int i = 0; i < 256; ++i) s += L.lsum[i];
+        row[kPB3] = gb3;
+        row[kNP] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_grad_reduce(int nblocks, const float* __restrict__ partial,
+                                                     float* __restrict__ grad /*[kNP + 1]*/) {
+    for (int p = blockIdx.x * 256 + threadIdx.x; p <= kNP; p += gridDim.x * 256) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * (kNP + 1) + p];
+        grad[p] = (float)s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ master, uint16_t* __restrict__ wbf,
+                                              float* __restrict__ mom, float* __restrict__ vel,
+                                              const float* __restrict__ grad, float lr, float b1, float b2,
+                                              float eps, int step) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < kNP; p += gridDim.x * 256) {
+        const float g = grad[p];
+        const float m = b1 * mom[p] + (1.0f - b1) * g;
+        const float v = b2 * vel[p] + (1.0f - b2) * g * g;
+        mom[p] = m;
+        vel[p] = v;
+        const float w = master[p] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+        master[p] = w;
+        wbf[p] = f32_to_bf16(w);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_refresh_bf16(const float* __restrict__ master, uint16_t* __restrict__ wbf) {
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < kNP; p += gridDim.x * 256) wbf[p] = f32_to_bf16(master[p]);
+}
+
+// Order-preserving map of float scores to uint32 keys: flip all bits of a
+// negative float, flip only the sign bit of a non-negative one.  NaN scores
+// are reported through *bad.
+__global__ __launch_bounds__(256) void k_score_keys(int64_t n, const float* __restrict__ score,
+                                                    uint32_t* __restrict__ keys, int* bad) {
+    for (int64_t v = blockIdx.x * 256LL + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const float s = score[v];
+        if (s != s) atomicOr(bad, 1);
+        const uint32_t u = __float_as_uint(s);
+        keys[v] = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    }
+}
+
+int grid_for(int64_t items, int per_block) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t want = (items + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 8));
+}
+
+// ---------------------------------------------------------------------------
+// Host: exact smallest-last ranks
+// ---------------------------------------------------------------------------
+
+// Repeatedly remove a vertex of minimum remaining degree, the smallest id
+// among those; the colouring order is the reverse removal order, rank[v] is
+// v's position in it.  Buckets per degree hold min-heaps of ids with lazy
+// deletion (an entry is live when its degree still matches).
+int32_t smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* rank) {
+    std::vector<int32_t> deg(n);
+    std::vector<char> gone(n, 0);
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t d = 0;
+        for (int32_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) d += col[p] != v;
+        deg[v] = d;
+        maxd = std::max(maxd, d);
+    }
+    using Heap = std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>>;
+    std::vector<Heap> bucket(maxd + 1);
+    for (int32_t v = 0; v < n; ++v) bucket[deg[v]].push(v);
+    int32_t cur = 0, degeneracy = 0;
+    for (int32_t removed = 0; removed < n; ++removed) {
+        int32_t v = -1;
+        for (;;) {
+            while (bucket[cur].empty()) ++cur;
+            const int32_t c = bucket[cur].top();
+            bucket[cur].pop();
+            if (!gone[c] && deg[c] == cur) {
+                v = c;
+                break;
+            }
+        }
+        gone[v] = 1;
+        degeneracy = std::max(degeneracy, cur);
+        rank[v] = n - 1 - removed;
+        for (int32_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) {
+            const int32_t w = col[p];
+            if (w == v || gone[w]) continue;
+            bucket[--deg[w]].push(w);
+            if (deg[w] < cur) cur = deg[w];
+        }
+    }
+    return degeneracy;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
+                    gcolor_stream_t stream) {
+    if (n < 0) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    if (!row_ptr || !feat_out) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_features<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, seed, feat_out);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_feature_stats(int64_t n, const float* feat, double* acc, gcolor_stream_t stream) {
+    if (n < 0 || !acc) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_feat_stats<<<grid_for(n, 256), 256, 0, st>>>(n, feat, acc);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_mlp_forward(int64_t n, const float* feat, const float* master, const uint16_t* wbf, const float* norm,
+                       float* score, gcolor_stream_t stream) {
+    if (n < 0 || !master || !wbf || !norm) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    if (!feat || !score) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_mlp_forward<<<grid_for(n, 256), 256, 0, st>>>(n, feat, master, wbf, norm, score);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+size_t gcolor_mlp_partial_floats(int32_t batch) {
+    if (batch <= 0) return 0;
+    const int tiles = (batch + kTile - 1) / kTile;
+    const int tpb = std::max(1, (tiles + 511) / 512);
+    const int blocks = (tiles + tpb - 1) / tpb;
+    return (size_t)blocks * (kNP + 1);
+}
+
+int gcolor_mlp_grad(int32_t batch, const int32_t* idx, const float* feat, const float* target, const float* master,
+                    const uint16_t* wbf, const float* norm, float* partial, float* grad, gcolor_stream_t stream) {
+    if (batch <= 0 || !idx || !feat || !target || !master || !wbf || !norm || !partial || !grad)
+        return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int tiles = (batch + kTile - 1) / kTile;
+    const int tpb = std::max(1, (tiles + 511) / 512);
+    const int blocks = (tiles + tpb - 1) / tpb;
+    k_mlp_backward<<<blocks, 256, 0, st>>>(batch, idx, feat, target, master, wbf, norm, partial, tpb);
+    if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
+    k_grad_reduce<<<(kNP + 256) / 256, 256, 0, st>>>(blocks, partial, grad);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_mlp_adam(float* master, uint16_t* wbf, float* mom, float* vel, const float* grad, float lr, float beta1,
+                    float beta2, float eps, int32_t step, gcolor_stream_t stream) {
+    if (!master || !wbf || !mom || !vel || !grad || step < 1) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_adam<<<(kNP + 255) / 256, 256, 0, st>>>(master, wbf, mom, vel, grad, lr, beta1, beta2, eps, step);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_mlp_refresh_bf16(const float* master, uint16_t* wbf, gcolor_stream_t stream) {
+    if (!master || !wbf) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_refresh_bf16<<<(kNP + 255) / 256, 256, 0, st>>>(master, wbf);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_scores_to_keys(int64_t n, const float* score, uint32_t* keys, int32_t* bad, gcolor_stream_t stream) {
+    if (n < 0 || !bad) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    if (!score || !keys) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_score_keys<<<grid_for(n, 256), 256, 0, st>>>(n, score, keys, bad);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* rank,
+                              int32_t* degeneracy) {
+    if (n < 0 || (n > 0 && (!row_ptr || !rank))) return GCOLOR_EINVAL;
+    if (n == 0) {
+        if (degeneracy) *degeneracy = 0;
+        return GCOLOR_OK;
+    }
+    if (row_ptr[n] > 0 && !col_idx) return GCOLOR_EINVAL;
+    const int32_t d = smallest_last_host(n, row_ptr, col_idx, rank);
+    if (degeneracy) *degeneracy = d;
+    return GCOLOR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""Pins of the learned-ordering oracle (CPU only): the hash against splitmix64's
+published first output, features against closed forms and brute force, the
+analytic gradient against central finite differences, BF16 rounding and the
+order-preserving key map; and the library's host smallest-last routine
+against the oracle's."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import learned as OL
+
+
+def test_mix_matches_splitmix64_reference():
+    # splitmix64 started from state 0 first returns mix(0 + GAMMA)
+    assert OL.mix_int(OL.GAMMA) == 0xE220A8397B1DCDAF
+    rng = np.random.default_rng(0)
+    vals = rng.integers(0, 2 ** 63, 200, dtype=np.uint64)
+    arr = OL.mix(vals)
+    assert all(int(a) == OL.mix_int(int(v)) for a, v in zip(arr, vals))
+
+
+def _adj(g):
+    return oracle.adjacency(g.row_ptr, g.col_idx)
+
+
+@pytest.mark.parametrize("n", [3, 4, 7, 12])
+def test_features_complete_graph(n):
+    g = graphgen.complete(n)
+    F = OL.features(g.row_ptr, g.col_idx)
+    d = n - 1
+    assert np.allclose(F[:, 0], d) and np.allclose(F[:, 2:5], d)
+    assert np.allclose(F[:, 1], np.log2(1 + d))
+    assert np.allclose(F[:, 5], d * (d - 1))
+    assert np.allclose(F[:, 6], d * (d - 1) / 2)  # every wedge closes
+    assert np.allclose(F[:, 7], d)
+
+
+def test_features_star_and_cycle():
+    n = 9
+    F = OL.features(*graphgen.star(n, 0)[1:])
+    assert F[0, 0] == n - 1 and F[0, 2] == F[0, 4] == 1 and F[0, 5] == 0 and F[0, 6] == 0 and F[0, 7] == 1
+    assert np.all(F[1:, 0] == 1) and np.all(F[1:, 3] == n - 1) and np.all(F[1:, 5] == n - 2)
+    assert np.all(F[1:, 6] == 0) and np.all(F[1:, 7] == 1)
+    C = OL.features(*graphgen.cycle(10)[1:])
+    assert np.all(C[:, 0] == 2) and np.all(C[:, 6] == 0) and np.all(C[:, 7] == 2)
+    T = OL.features(*graphgen.cycle(3)[1:])
+    assert np.all(T[:, 6] == 1)  # the single wedge of a triangle vertex closes
+
+
+def test_features_against_loops():
+    g = graphgen.rmat(9, 8, (0.55, 0.15, 0.15), 3)
+    adj = _adj(g)
+    deg = [len(a) for a in adj]
+    F = OL.features(g.row_ptr, g.col_idx, seed=11)
+    eset = {(u, w) for u in range(g.n) for w in adj[u]}
+    for v in range(g.n):
+        nd = [deg[w] for w in adj[v]]
+        d = deg[v]
+        h = max([k for k in range(d + 1) if sum(1 for x in nd if x >= k) >= k], default=0)
+        assert F[v, 7] == h
+        if d:
+            assert F[v, 2] == min(nd) and F[v, 4] == max(nd) and np.isclose(F[v, 3], sum(nd) / d)
+            assert F[v, 5] == sum(x - 1 for x in nd)
+        if d >= 2:
+            closed = 0
+            for i in range(8):
+                hh = OL.mix_int(11 * OL.GAMMA + OL.mix_int(8 * v + i + 1))
+                a = (hh & 0xFFFFFFFF) % d
+                b = (hh >> 32) % (d - 1)
+                b += b >= a
+                closed += (adj[v][a], adj[v][b]) in eset
+            assert np.isclose(F[v, 6], closed / 8 * d * (d - 1) / 2)
+
+
+def _random_model(seed):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.4, OL.NPARAM)
+    return OL.params_from_vector(p), p
+
+
+def test_gradient_matches_finite_differences():
+    params, p = _random_model(1)
+    rng = np.random.default_rng(2)
+    X = rng.normal(0, 1, (37, OL.NF))
+    t = rng.uniform(0, 1, 37)
+    g, _ = OL.grad(X, t, params)
+    h = 1e-6
+    for j in list(range(0, OL.NPARAM, 97)) + [OL.B3, OL.W3 + 5, OL.B1 + 3, OL.B2 + 7]:
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (OL.loss(X, t, OL.params_from_vector(pp)) - OL.loss(X, t, OL.params_from_vector(pm))) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 * max(1.0, abs(fd)), (j, fd, g[j])
+
+
+def test_gradient_descent_reduces_loss():
+    rng = np.random.default_rng(4)
+    p = rng.normal(0, 0.1, OL.NPARAM)
+    params = OL.params_from_vector(p)
+    X = rng.normal(0, 1, (200, OL.NF))
+    t = np.tanh(X[:, 0]) * 0.5 + 0.5
+    l0 = OL.loss(X, t, params)
+    for _ in range(200):
+        g, _ = OL.grad(X, t, OL.params_from_vector(p))
+        p = p - 0.02 * g
+    assert OL.loss(X, t, OL.params_from_vector(p)) < 0.5 * l0
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 3.14159, 0.0], dtype=np.float32)
+    r = OL.bf16_round(vals)
+    assert r[0] == 1.0 and r[1] == 1.0  # halfway: ties to even
+    assert r[2] == 1.0 + 2 ** -7        # above halfway rounds up
+    assert r[3] == -2.5 and r[5] == 0.0
+    assert abs(r[4] - 3.14159) < 2 ** -7 * 4
+
+
+def test_keys_preserve_order():
+    rng = np.random.default_rng(5)
+    s = np.concatenate([rng.normal(0, 3, 500), [0.0, -0.0, 1e-30, -1e-30, 1e30, -1e30]]).astype(np.float32)
+    k = OL.keys_from_scores(s).astype(np.int64)
+    lt = s[:, None] < s[None, :]
+    assert np.all(k[:, None] < k[None, :], where=lt)      # strictly ordered where the scores are
+    eq = (s[:, None] == s[None, :]) & (np.signbit(s)[:, None] == np.signbit(s)[None, :])
+    assert np.all(k[:, None] == k[None, :], where=eq)     # equal scores, equal keys (-0.0 below +0.0)
+
+
+def test_library_host_smallest_last_matches_oracle():
+    """The library's host smallest-last routine (the training targets) against
+    the oracle's, on random and structured graphs."""
+    from paper_1205_3809_amd import learned as L
+    for g in [graphgen.rmat(12, 16, (0.57, 0.19, 0.19), 1), graphgen.uniform(3000, 15000, 2),
+              graphgen.grid((20, 30), True), graphgen.complete(9), graphgen.star(50, 17), graphgen.empty(4)]:
+        r, d = L.smallest_last_rank(g.row_ptr, g.col_idx)
+        ro, do = oracle.smallest_last_rank(g.row_ptr, g.col_idx)
+        assert np.array_equal(r, ro) and d == do
