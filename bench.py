@@ -32,6 +32,10 @@ WORKLOADS = {
     # stencil grids with 5% extra random edges, random geometric graphs with
     # mean degree 6..27; natural order; one persistent launch per step
     "batch4096": ("batch", dict(count=4096, seed=2026, log2_lo=8, log2_hi=16)),
+    # learned ordering: train on 256 R-MAT scale-16 edge-factor-16 graphs
+    # (0.57, 0.19, 0.19, 0.05), seeds 0..255; evaluate on scale 22, seed 1000
+    "learned22": ("learned", dict(train_graphs=256, train_scale=16, eval_scale=22, edge_factor=16,
+                                  abcd=(0.57, 0.19, 0.19, 0.05), eval_seed=1000, epochs=4, batch=65536)),
 }
 
 
@@ -136,6 +140,8 @@ def main():
 
     if WORKLOADS[args.workload][0] == "batch" and args.gpus == 1:
         return bench_batch(args)
+    if WORKLOADS[args.workload][0] == "learned" and args.gpus == 1:
+        return bench_learned(args)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
               "sharding of the method is described in the design notes but not built." % args.gpus,
@@ -398,6 +404,80 @@ def bench_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bmin / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_model": "lower bound: 4 B per row entry + 8 B per vertex"},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_learned(args):
+    """Learned ordering vs natural order vs exact smallest-last on the
+    evaluation graph; every timed path starts from the graph resident in HBM
+    and ends with the colours in HBM."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1205_3809_amd as gc
+    from paper_1205_3809_amd import learned as L
+
+    p = WORKLOADS[args.workload][1]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    train = [graphgen.rmat(p["train_scale"], p["edge_factor"], p["abcd"][:3], s) for s in range(p["train_graphs"])]
+    log("%d training graphs built in %.1fs" % (len(train), time.time() - t0))
+    model = L.MLP(seed=0)
+    t0 = time.time()
+    rep = L.train(model, [(g.row_ptr, g.col_idx) for g in train], epochs=p["epochs"], batch=p["batch"], lr=2e-3,
+                  log=log)
+    train_s = time.time() - t0
+    del train
+    ev = graphgen.rmat(p["eval_scale"], p["edge_factor"], p["abcd"][:3], p["eval_seed"])
+    log("eval graph n=%d nnz=%d" % (ev.n, ev.nnz))
+    rp = torch.from_numpy(ev.row_ptr).to(dev)
+    ci = torch.from_numpy(ev.col_idx).to(dev)
+    out = torch.empty(ev.n, dtype=torch.int32, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        w = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - w) * 1000.0 / reps, r
+
+    def natural():
+        return gc.color_graph_ex(rp, ci, None, out, stats=True)[1].num_colors
+
+    def learned():
+        keys, _ = L.order_learned(model, rp, ci)
+        return gc.color_graph_ex(rp, ci, keys, out, stats=True)[1].num_colors
+
+    def learned_fb():
+        return L.color_learned(model, rp, ci, fallback=True)
+
+    reps = max(1, args.steps)
+    t_nat, c_nat = timed(natural, reps)
+    t_learn, c_learn = timed(learned, reps)
+    t_fb, fb = timed(learned_fb, reps)
+    # exact smallest-last: the library's host routine (the order is a
+    # sequential peel), keys to the device, same colouring
+    w = time.perf_counter()
+    rank, degen = L.smallest_last_rank(ev.row_ptr, ev.col_idx)
+    t_sl_order = (time.perf_counter() - w) * 1000.0
+    slk = torch.from_numpy(rank.astype(np.int32)).to(dev)
+    t_sl_col, c_sl = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, stats=True)[1].num_colors, reps)
+    res = {
+        "metric": "learned ordering: colours and end-to-end ms vs natural order and exact smallest-last",
+        "value": round(t_learn, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": reps,
+        "dtype": "int32 colouring; bf16 weights, fp32 accumulation", "data": "synthetic",
+        "config": {"workload": args.workload, "eval_n": ev.n, "eval_nnz": ev.nnz, **{k: v for k, v in p.items()}},
+        "colours": {"natural": c_nat, "learned": c_learn, "learned_with_fallback": int(min(fb[2], fb[3])),
+                    "exact_smallest_last": c_sl, "degeneracy_plus_1": degen + 1},
+        "ms": {"natural": round(t_nat, 3), "learned": round(t_learn, 3), "learned_with_fallback": round(t_fb, 3),
+               "exact_smallest_last_order_host": round(t_sl_order, 1),
+               "exact_smallest_last_total": round(t_sl_order + t_sl_col, 1)},
+        "training": {"seconds": round(train_s, 2), "vertices": rep.vertices, "final_minibatch_loss":
+                     round(rep.losses[-1], 6)},
     }
     print(json.dumps(res), flush=True)
 
