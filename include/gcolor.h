@@ -196,7 +196,11 @@ int gcolor_wall_clock_khz(int32_t* khz);
  * triangle estimate from 8 hashed wedges (closed fraction times
  * degree (degree - 1) / 2; wedge choices are splitmix64 of (seed, vertex,
  * sample)), and the h-index of the neighbour degrees (a core-number
- * estimate).  Rows must be sorted ascending.
+ * estimate).  Rows must be sorted ascending.  Vertices of degree >= 128 are
+ * listed in a buffer the library allocates per device on first use (4 (n + 64)
+ * bytes, grown for larger n) and processed one workgroup each; concurrent
+ * calls on one device from different streams share that buffer and race.
+ * Errors: GCOLOR_EINVAL (n < 0, NULL pointers with n > 0), GCOLOR_EHIP.
  */
 int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
                     gcolor_stream_t stream);

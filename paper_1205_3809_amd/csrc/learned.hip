@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <thread>
 #include <vector>
@@ -66,16 +67,50 @@ __device__ __forceinline__ bool has_edge(const int* __restrict__ row_ptr, const 
     return false;
 }
 
-// One vertex per group of GS lanes.  Features (float, raw):
+// Features (float, raw):
 //  0 degree            1 log2(1 + degree)
 //  2 min neighbour degree   3 mean neighbour degree   4 max neighbour degree
 //  5 two-hop paths: sum over neighbours of (degree - 1)
 //  6 triangle estimate: closed fraction of 8 hashed wedges * deg (deg-1) / 2
 //  7 core estimate: h-index of the neighbour degrees
+//
+// Vertices below kFeatHeavy neighbours take a group of 8 lanes; the others
+// are appended to a list and take a whole workgroup each (k_features_heavy),
+// so that one hub row does not serialise the launch.
+constexpr int kFeatHeavy = 128;
+constexpr int kHistBins = 4096;
+
+__device__ __forceinline__ uint64_t wedge_hash(uint64_t seed, int v, int i) {
+    return mix64(seed * 0x9E3779B97F4A7C15ULL + mix64((uint64_t)v * 8ULL + (uint64_t)i + 1ULL));
+}
+
+// Sample i of vertex v (degree d >= 2, row at s): 1 if the wedge closes.
+__device__ __forceinline__ int wedge_closed(const int* __restrict__ row_ptr, const int* __restrict__ col, int v,
+                                            int s, int d, int i, uint64_t seed) {
+    const uint64_t h = wedge_hash(seed, v, i);
+    const int a = (int)((h & 0xffffffffULL) % (uint64_t)d);
+    int b = (int)((h >> 32) % (uint64_t)(d - 1));
+    if (b >= a) b += 1;
+    return has_edge(row_ptr, col, col[s + a], col[s + b]) ? 1 : 0;
+}
+
+__device__ __forceinline__ void write_features(float* __restrict__ out, int v, int d, int mn, int mx, long long sum,
+                                               int closed, int h) {
+    float* f = out + (size_t)v * kF;
+    f[0] = (float)d;
+    f[1] = log2f(1.0f + (float)d);
+    f[2] = d ? (float)mn : 0.0f;
+    f[3] = d ? (float)((double)sum / (double)d) : 0.0f;
+    f[4] = (float)mx;
+    f[5] = (float)(sum - d);
+    f[6] = d >= 2 ? (float)((double)closed / kWedges * 0.5 * (double)d * (double)(d - 1)) : 0.0f;
+    f[7] = (float)h;
+}
+
+// One vertex of degree < kFeatHeavy per group of GS lanes.
 template <int GS>
-__device__ void features_vertex(int v, int lig, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                                uint64_t seed, float* __restrict__ out) {
-    const int s = row_ptr[v], e = row_ptr[v + 1];
+__device__ void features_light(int v, int s, int e, int lig, const int* __restrict__ row_ptr,
+                               const int* __restrict__ col, uint64_t seed, float* __restrict__ out) {
     const int d = e - s;
     int mn = 0x7fffffff, mx = 0;
     long long sum = 0;
@@ -92,8 +127,9 @@ __device__ void features_vertex(int v, int lig, const int* __restrict__ row_ptr,
         mx = max(mx, __shfl_xor(mx, o, GS));
         sum += __shfl_xor(sum, o, GS);
     }
-    // h-index: largest h with at least h neighbours of degree >= h (binary search)
-    int lo = 0, hi = d;
+    // h-index: largest h with at least h neighbours of degree >= h; h is at
+    // most min(d, max neighbour degree); binary search over that range
+    int lo = 0, hi = min(d, mx);
     while (lo < hi) {
         const int h = (lo + hi + 1) >> 1;
         int c = 0;
@@ -103,41 +139,178 @@ __device__ void features_vertex(int v, int lig, const int* __restrict__ row_ptr,
         if (c >= h) lo = h;
         else hi = h - 1;
     }
-    // wedges: lane i < kWedges samples wedge i
     int closed = 0;
-    if (d >= 2) {
-        for (int i = lig; i < kWedges; i += GS) {
-            const uint64_t h = mix64(seed * 0x9E3779B97F4A7C15ULL + mix64((uint64_t)v * 8ULL + (uint64_t)i + 1ULL));
-            const int a = (int)((h & 0xffffffffULL) % (uint64_t)d);
-            int b = (int)((h >> 32) % (uint64_t)(d - 1));
-            if (b >= a) b += 1;
-            closed += has_edge(row_ptr, col, col[s + a], col[s + b]) ? 1 : 0;
-        }
-    }
+    if (d >= 2)
+        for (int i = lig; i < kWedges; i += GS) closed += wedge_closed(row_ptr, col, v, s, d, i, seed);
 #pragma unroll
     for (int o = GS / 2; o > 0; o >>= 1) closed += __shfl_xor(closed, o, GS);
-    if (lig == 0) {
-        float* f = out + (size_t)v * kF;
-        f[0] = (float)d;
-        f[1] = log2f(1.0f + (float)d);
-        f[2] = d ? (float)mn : 0.0f;
-        f[3] = d ? (float)((double)sum / (double)d) : 0.0f;
-        f[4] = (float)mx;
-        f[5] = (float)(sum - d);
-        f[6] = d >= 2 ? (float)((double)closed / kWedges * 0.5 * (double)d * (double)(d - 1)) : 0.0f;
-        f[7] = (float)lo;
-    }
+    if (lig == 0) write_features(out, v, d, mn, mx, sum, closed, lo);
 }
 
 __global__ __launch_bounds__(256) void k_features(int n, const int* __restrict__ row_ptr,
                                                   const int* __restrict__ col, uint64_t seed,
-                                                  float* __restrict__ out) {
+                                                  float* __restrict__ out, int* __restrict__ heavy,
+                                                  int* __restrict__ heavy_count) {
     // 8 lanes per vertex covers the sampled wedges in one pass
     constexpr int GS = 8;
     const int groups = gridDim.x * (256 / GS);
     const int lig = threadIdx.x & (GS - 1);
-    for (int v = blockIdx.x * (256 / GS) + threadIdx.x / GS; v < n; v += groups)
-        features_vertex<GS>(v, lig, row_ptr, col, seed, out);
+    const int lane = threadIdx.x & 63;
+    for (int v = blockIdx.x * (256 / GS) + threadIdx.x / GS; v < n; v += groups) {
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        const bool big = e - s >= kFeatHeavy;
+        // wave-aggregated append of the heavy vertices (one lane per group)
+        const bool app = big && lig == 0;
+        const unsigned long long m = __ballot(app);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(heavy_count, __popcll(m));
+            base = __shfl(base, leader);
+            if (app) heavy[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+        }
+        if (!big) features_light<GS>(v, s, e, lig, row_ptr, col, seed, out);
+    }
+}
+
+struct HeavyLds {
+    int hist[kHistBins];
+    int scan[256];
+    int wi[4], wj[4];
+    long long wl[4];
+};
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Block-wide sum / max over 256 threads (every thread gets the result).
+__device__ int block_sum(HeavyLds* L, int x) {
+    x = wave_sum(x);
+    if ((threadIdx.x & 63) == 0) L->wi[threadIdx.x >> 6] = x;
+    __syncthreads();
+    const int r = L->wi[0] + L->wi[1] + L->wi[2] + L->wi[3];
+    __syncthreads();
+    return r;
+}
+
+__device__ int block_max(HeavyLds* L, int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    if ((threadIdx.x & 63) == 0) L->wi[threadIdx.x >> 6] = x;
+    __syncthreads();
+    const int r = max(max(L->wi[0], L->wi[1]), max(L->wi[2], L->wi[3]));
+    __syncthreads();
+    return r;
+}
+
+// One vertex of degree >= kFeatHeavy per workgroup of 256 threads.
+// h-index by histogram refinement: it lies in [lo, hi] with f(lo) >= lo,
+// where f(k) = number of neighbours of degree >= k.  One pass over the row
+// histograms the (clamped) degrees in [lo, hi] into at most kHistBins buckets
+// of width W; the largest bucket start k with f(k) >= k narrows the range to
+// that bucket, and width 1 gives h exactly (at most three passes for any
+// 32-bit degree, one when the range is below kHistBins).
+__device__ void features_heavy(HeavyLds* L, int v, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                               uint64_t seed, float* __restrict__ out) {
+    const int tid = threadIdx.x;
+    const int s = row_ptr[v], e = row_ptr[v + 1];
+    const int d = e - s;
+    int mn = 0x7fffffff, mx = 0;
+    long long sum = 0;
+    for (int p = s + tid; p < e; p += 256) {
+        const int w = col[p];
+        const int dw = row_ptr[w + 1] - row_ptr[w];
+        mn = min(mn, dw);
+        mx = max(mx, dw);
+        sum += dw;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o));
+        mx = max(mx, __shfl_xor(mx, o));
+        sum += __shfl_xor(sum, o);
+    }
+    if ((tid & 63) == 0) {
+        L->wi[tid >> 6] = mn;
+        L->wj[tid >> 6] = mx;
+        L->wl[tid >> 6] = sum;
+    }
+    __syncthreads();
+    mn = min(min(L->wi[0], L->wi[1]), min(L->wi[2], L->wi[3]));
+    mx = max(max(L->wj[0], L->wj[1]), max(L->wj[2], L->wj[3]));
+    sum = L->wl[0] + L->wl[1] + L->wl[2] + L->wl[3];
+    __syncthreads();
+
+    const int cap = min(d, mx);
+    int lo = 0, hi = cap;
+    for (;;) {
+        const int span = hi - lo + 1;
+        const int W = (span + kHistBins - 1) / kHistBins;
+        const int nb = (span + W - 1) / W;
+        for (int j = tid; j < nb; j += 256) L->hist[j] = 0;
+        __syncthreads();
+        int above = 0;
+        for (int p = s + tid; p < e; p += 256) {
+            const int w = col[p];
+            const int c = min(row_ptr[w + 1] - row_ptr[w], cap);
+            if (c > hi) ++above;
+            else if (c >= lo) atomicAdd(&L->hist[(c - lo) / W], 1);
+        }
+        above = block_sum(L, above);  // its barrier also completes the histogram
+        // thread t owns buckets [t * per, min(nb, (t + 1) * per))
+        const int per = (nb + 255) / 256;
+        const int j0 = min(nb, tid * per), j1 = min(nb, j0 + per);
+        int cs = 0;
+        for (int j = j0; j < j1; ++j) cs += L->hist[j];
+        // inclusive suffix sums of the chunk sums (Hillis-Steele)
+        L->scan[tid] = cs;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int add = tid + o < 256 ? L->scan[tid + o] : 0;
+            __syncthreads();
+            L->scan[tid] += add;
+            __syncthreads();
+        }
+        int run = above + L->scan[tid] - cs;  // neighbours in later chunks or above hi
+        int best = -1;
+        for (int j = j1 - 1; j >= j0; --j) {
+            run += L->hist[j];
+            if (run >= lo + j * W) {
+                best = j;
+                break;
+            }
+        }
+        best = block_max(L, best);
+        lo += best * W;
+        if (W == 1) break;
+        hi = min(hi, lo + W - 1);
+    }
+    int closed = 0;
+    if (tid < 64) {
+        if (tid < kWedges) closed = wedge_closed(row_ptr, col, v, s, d, tid, seed);
+        closed = wave_sum(closed);
+    }
+    if (tid == 0) write_features(out, v, d, mn, mx, sum, closed, lo);
+}
+
+__global__ __launch_bounds__(256) void k_features_heavy(const int* __restrict__ row_ptr,
+                                                        const int* __restrict__ col, uint64_t seed,
+                                                        const int* __restrict__ heavy,
+                                                        const int* __restrict__ heavy_count,
+                                                        float* __restrict__ out) {
+    __shared__ HeavyLds L;
+    const int total = *heavy_count;
+    for (int i = blockIdx.x; i < total; i += gridDim.x) {
+        features_heavy(&L, heavy[i], row_ptr, col, seed, out);
+        __syncthreads();  // LDS reuse by the next vertex
+    }
+}
+
+__global__ void k_zero_count(int* c) {
+    if (threadIdx.x == 0) c[0] = 0;
 }
 
 // Per-feature sum and sum of squares of log1p(feature), in double.
@@ -432,6 +605,37 @@ __global__ __launch_bounds__(256) void k_score_keys(int64_t n, const float* __re
     }
 }
 
+// Per-device buffer for the heavy-vertex list of gcolor_features: a count
+// (padded to 256 bytes) and up to n vertex ids; grown on demand.
+struct HeavyBuf {
+    int* p = nullptr;
+    int64_t cap = 0;
+};
+std::mutex g_heavy_mu;
+std::vector<HeavyBuf> g_heavy;
+
+hipError_t heavy_buffer(int n, int** out) {
+    int dev = 0;
+    hipError_t rc = hipGetDevice(&dev);
+    if (rc != hipSuccess) return rc;
+    std::lock_guard<std::mutex> g(g_heavy_mu);
+    if ((int)g_heavy.size() <= dev) g_heavy.resize(dev + 1);
+    HeavyBuf& b = g_heavy[dev];
+    if (b.cap < n) {
+        if (b.p) {
+            rc = hipFree(b.p);
+            b.p = nullptr;
+            b.cap = 0;
+            if (rc != hipSuccess) return rc;
+        }
+        rc = hipMalloc((void**)&b.p, ((size_t)n + 64) * sizeof(int));
+        if (rc != hipSuccess) return rc;
+        b.cap = n;
+    }
+    *out = b.p;
+    return hipSuccess;
+}
+
 int grid_for(int64_t items, int per_block) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -495,7 +699,14 @@ int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, u
     if (n == 0) return GCOLOR_OK;
     if (!row_ptr || !feat_out) return GCOLOR_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    k_features<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, seed, feat_out);
+    int* buf = nullptr;
+    if (heavy_buffer(n, &buf) != hipSuccess) return GCOLOR_EHIP;
+    int* count = buf;
+    int* list = buf + 64;
+    k_zero_count<<<1, 64, 0, st>>>(count);
+    k_features<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, seed, feat_out, list, count);
+    // one workgroup per listed vertex (grid-strided over the device count)
+    k_features_heavy<<<grid_for(n, kFeatHeavy), 256, 0, st>>>(row_ptr, col_idx, seed, list, count, feat_out);
     return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
 }
 

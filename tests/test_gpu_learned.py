@@ -18,9 +18,25 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+def hub_of_hubs(d=6000, top=9000, pool=10000):
+    """Vertex 0 joined to 1..d; vertex i also joined to top // i vertices of a
+    pool: neighbour degrees reach top + 1, so the hub's h-index search range
+    (min(degree, max neighbour degree) = d > 4096) takes more than one
+    histogram pass."""
+    src = [np.zeros(d, np.int64)]
+    dst = [np.arange(1, d + 1)]
+    rng = np.random.default_rng(3)
+    for i in range(1, d + 1):
+        k = top // i
+        src.append(np.full(k, i))
+        dst.append(d + 1 + rng.choice(pool, k, replace=False))
+    return graphgen.from_pairs(d + 1 + pool, np.concatenate(src), np.concatenate(dst))
+
+
 def test_features_match_oracle():
     from paper_1205_3809_amd import learned as L
-    for g in [graphgen.rmat(14, 16, TRAIN_ABCD, 5), graphgen.grid((30, 40), True), graphgen.complete(20),
+    for g in [graphgen.rmat(14, 16, TRAIN_ABCD, 5), graphgen.rmat(17, 16, TRAIN_ABCD, 9), hub_of_hubs(),
+              graphgen.grid((30, 40), True), graphgen.complete(20), graphgen.complete(300),
               graphgen.star(5000, 3), graphgen.empty(7)]:
         got = L.features(dev(g.row_ptr), dev(g.col_idx), 123).cpu().numpy().astype(np.float64)
         ref = OL.features(g.row_ptr, g.col_idx, 123)
