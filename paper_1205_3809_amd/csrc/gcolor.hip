@@ -607,6 +607,81 @@ __device__ __forceinline__ uint64_t state_window(int start, int e, int base, con
 // Row entries kept in registers: up to kCache per lane.
 constexpr int kCache = 8;
 
+// Long rows (beyond the register cache) of the wave and workgroup tiers:
+// first-fit in one pass over the row.  Colours 1..64 collect in a per-lane
+// mask, colours 65..64 + kFFBits in an LDS bitmap (one per wave for the wave
+// tier).  Returns the first free colour, or 0 when all of 1..64 + kFFBits are
+// taken (the caller continues with 64-colour windows above that range).
+constexpr int kFFWords = 128;
+constexpr int kFFBits = kFFWords * 32;
+
+template <int GS>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (GS == kBlock) {
+        __syncthreads();
+    } else {
+        static_assert(GS == kWave, "wave or workgroup groups only");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ int first_fit_long(const int* __restrict__ colp, const S* __restrict__ st, int start,
+                                              int e, unsigned* bm, uint64_t* red, int* shc) {
+    const int lig = threadIdx.x & (GS - 1);
+    for (int i = lig; i < kFFWords; i += GS) bm[i] = 0u;
+    group_sync<GS>();
+    uint64_t m = 0;
+    for (int p0 = start; p0 < e; p0 += 4 * GS) {
+        int x[4], c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * GS;
+            x[j] = p < e ? colp[p] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? -(int)st[x[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned lo = (unsigned)(c[j] - 1), hi = (unsigned)(c[j] - 65);
+            if (lo < 64u) m |= 1ull << lo;
+            else if (hi < (unsigned)kFFBits) atomicOr(&bm[hi >> 5], 1u << (hi & 31));
+        }
+    }
+    if constexpr (GS == kBlock) {
+        m = group_or<kWave>(m);
+        if (__lane_id() == 0) red[threadIdx.x / kWave] = m;
+        __syncthreads();  // also completes the bitmap
+        m = red[0] | red[1] | red[2] | red[3];
+    } else {
+        m = group_or<GS>(m);
+        group_sync<GS>();
+    }
+    int pos = 0x7fffffff;
+    if (~m) {
+        pos = __builtin_ctzll(~m) - 64;
+    } else {
+        for (int i = lig; i < kFFWords; i += GS) {
+            const unsigned z = ~bm[i];
+            if (z) {
+                pos = min(pos, i * 32 + __builtin_ctz(z));
+                break;
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) pos = min(pos, __shfl_xor(pos, o));
+        if constexpr (GS == kBlock) {
+            if (__lane_id() == 0) shc[threadIdx.x / kWave] = pos;
+            __syncthreads();
+            pos = min(min(shc[0], shc[1]), min(shc[2], shc[3]));
+        }
+    }
+    group_sync<GS>();  // red / shc / bitmap free for reuse
+    return pos == 0x7fffffff ? 0 : 65 + pos;
+}
+
 // Evaluation of one entry (x with word sx at row position p) of dirty vertex
 // w after its new colour `now` is known.  Preceding clean neighbours count
 // toward w's counter; later clean neighbours holding old / now get -1 / +1
@@ -659,7 +734,7 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, co
 // to the k_inc_b list or, when its count is final and 0, to the candidates.
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* stgb, int k, int w, int lig,
-                                             uint64_t* red, int* shc, long long* dedges) {
+                                             uint64_t* red, int* shc, unsigned* ffbm, long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
     const int cs = cset(k);
@@ -678,8 +753,15 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
         for (int j = 0; j < kCache; ++j) sv[j] = st[xs[j]];  // p >= e reads w's own (positive) word
     }
     // new tentative colour: first window of 64 colours with a free slot
-    int now;
-    for (int base = 1;; base += 64) {
+    int now = 0, base0 = 1;
+    if constexpr (GS == kBlock || GS == kWave) {
+        if (!cached) {
+            unsigned* bm = GS == kBlock ? ffbm : ffbm + (threadIdx.x / kWave) * kFFWords;
+            now = first_fit_long<GS, S>(a.colp, st, s + lig, e, bm, red, shc);
+            base0 = 65 + kFFBits;
+        }
+    }
+    for (int base = base0; now == 0; base += 64) {
         uint64_t m = 0;
         if (cached) {
 #pragma unroll
@@ -699,10 +781,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
         } else {
             m = group_or<GS>(m);
         }
-        if (~m) {
-            now = base + __builtin_ctzll(~m);
-            break;
-        }
+        if (~m) now = base + __builtin_ctzll(~m);
     }
     // counters
     int cnt = 0;
@@ -748,11 +827,11 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
 
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, Stage* stgb, int k, const int* list, int cnt,
-                                            int local, long long* dedges) {
+                                            int local, unsigned* ffbm, long long* dedges) {
     constexpr int CV = kBlock / GS;
     const int lig = threadIdx.x & (GS - 1);
     const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, dedges);
+    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, ffbm, dedges);
 }
 
 // Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
@@ -763,6 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     __shared__ int shc[8];
     __shared__ Stage stg;
     __shared__ Stage stgb;
+    __shared__ unsigned ffbm[(kBlock / kWave) * kFFWords];
     if (blockIdx.x == 0 && threadIdx.x == 0 && k - 1 < kMaxLog) {
         long long nd = 0;
         for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dlist(k)][b];
@@ -789,8 +869,8 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     stage_init(&stg);
     stage_init(&stgb);
     long long dedges = 0;
-#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, &dedges)
-#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, &dedges)
+#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, ffbm, &dedges)
+#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, &dedges)
 #define A_AFTER()                                \
     {                                            \
         stage_maybe_flush(a, &stg, cset(k));     \

@@ -86,6 +86,44 @@ def test_complete_graphs_many_windows(n):
     assert st.num_colors == n and st.rounds == n
 
 
+@pytest.mark.parametrize("n,order", [(600, "natural"), (600, "perm"), (2100, "natural"), (2100, "perm"),
+                                     (4300, "natural"), (4300, "perm")])
+def test_complete_long_rows(n, order):
+    """K_n with rows beyond the register cache of the wave tier (600) and the
+    workgroup tier (2100), and with more than 64 + 4096 colours (4300).
+    Closed form: the vertex of rank r in (key, id) order gets colour r + 1, in
+    n rounds; the oracle is not needed."""
+    import paper_1205_3809_amd as gc
+    g = graphgen.complete(n)
+    key = None if order == "natural" else graphgen.random_priority(n, 17)
+    engines = ENGINES if n <= 2100 else ENGINES[:1]
+    for name, flags in engines:
+        print("case complete-long n=%d order=%s engine=%s" % (n, order, name), flush=True)
+        col, st = gpu_color(g, key, flags=flags)
+        rank = np.arange(n) if key is None else np.argsort(np.argsort(key.astype(np.int64), kind="stable"))
+        assert np.array_equal(col, rank + 1), name
+        assert st.rounds == n and st.num_colors == n, name
+
+
+def clique_plus_hub(m, leaves):
+    """Clique on 0..m-1, leaves m..m+leaves-1, and a hub (the last id) joined
+    to every clique vertex and every leaf: the hub's long row stays dirty
+    while the clique commits one colour per round."""
+    hub = m + leaves
+    iu, ju = np.triu_indices(m, 1)
+    src = np.concatenate([iu, np.full(m + leaves, hub)])
+    dst = np.concatenate([ju, np.arange(m + leaves)])
+    return graphgen.from_pairs(hub + 1, src, dst)
+
+
+@pytest.mark.parametrize("m,leaves", [(70, 600), (300, 600), (300, 3000), (130, 9000)])
+def test_long_dirty_rows(m, leaves):
+    """Long rows that stay dirty for many rounds (wave and workgroup tiers,
+    colours past the first 64-colour window), against the oracle."""
+    col, st = check(clique_plus_hub(m, leaves), label="clique+hub")
+    assert col[-1] == m + 1
+
+
 @pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (32767, 5), (32768, 5), (70000, 123)])
 def test_star_hubs(n, center):
     """A centre of degree up to 70k runs on the workgroup-per-vertex bin."""
