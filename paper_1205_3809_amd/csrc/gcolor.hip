@@ -59,6 +59,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
+// Rows longer than this (the register cache of a wave) keep an active copy in
+// the wave and workgroup tiers of the incremental engine.
+constexpr int kHeavyDeg = 512;
+// Words per heavy row of the dropped-colour bitmap: colours 1..64, then
+// 65..4160, then padding.
+constexpr int kFW = 132;
 constexpr int kBins = 5;
 constexpr int kSets = 6;          // list sets (plain: 0,1 worklist ping-pong; incremental: see below)
 constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
@@ -89,7 +95,8 @@ struct Ctl {
     int32_t maxcolor;
     int32_t maxdeg;
     unsigned long long committed;  // vertices committed so far
-    int32_t pad[10];
+    int32_t nheavy;                // (incremental) rows with an active copy
+    int32_t pad[9];
 };
 static_assert(sizeof(Ctl) == 320, "ctl layout");
 
@@ -111,6 +118,14 @@ struct Args {
     Ctl* ctl;
     long long* __restrict__ log;   // [kMaxLog][kLogW]
     BinCfg cfg;
+    // (incremental) heavy rows: id per vertex of degree > kHeavyDeg, per id
+    // (preceding active, later active, buffer, -) and the dropped-colour
+    // bitmap; two active-row buffers indexed like col_idx
+    int* __restrict__ hid;
+    int4* __restrict__ hrow;
+    unsigned* __restrict__ hF;
+    int* __restrict__ act;
+    long long nnz;
 };
 
 struct Stage {
@@ -573,6 +588,22 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
             a.stamp[v] = 0;
             a.cflag[v] = 0;
         }
+        // heavy rows: an id each (wave-aggregated) and the whole row as the
+        // initial active view in the original buffer; the bitmap is written
+        // at the first compaction
+        const bool heavy = ok && deg > kHeavyDeg;
+        const unsigned long long hm = __ballot(heavy);
+        if (hm) {
+            const int leader = __ffsll((long long)hm) - 1;
+            int hb = 0;
+            if (__lane_id() == leader) hb = atomicAdd(&a.ctl->nheavy, __popcll(hm));
+            hb = __shfl(hb, leader);
+            if (heavy) {
+                const int h = hb + __popcll(hm & __lanemask_lt());
+                a.hid[v] = h;
+                a.hrow[h] = make_int4(sp, deg - sp, 0, 0);
+            }
+        }
         stage_append(a, &stg, ok && sp == 0, v, deg, cset(1));
         stage_maybe_flush(a, &stg, cset(1));
     }
@@ -705,6 +736,217 @@ __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __rest
     return atomicExch(&a.cflag[x], k) != k;
 }
 
+
+// Heavy rows (degree > kHeavyDeg) in the wave and workgroup tiers keep an
+// active copy: the neighbours not committed yet, plus committed ones whose
+// colour lies above the bitmap range, in two segments at the row's offsets
+// (preceding neighbours at s, later ones at s + split) of one of two buffers;
+// the colours of the committed neighbours dropped from it are kept in a
+// per-row bitmap (colours 1..64 + kFFBits).  Buffer 0 is the original row.
+// The set of uncommitted neighbours is all that the counters and the dirty
+// marks look at, and the committed colours only grow, so each dirty visit
+// scans the active row instead of the full row; the visit rewrites the
+// active row into the other buffer once a quarter of it has committed.
+struct HeavyView {
+    const int* row;
+    int s0, s1;   // segment starts
+    int pa, la;   // segment lengths
+    int buf, h;
+};
+
+__device__ __forceinline__ HeavyView heavy_view(const Args& a, int v, int s) {
+    HeavyView hv;
+    hv.h = a.hid[v];
+    const int4 r = a.hrow[hv.h];
+    hv.pa = r.x;
+    hv.la = r.y;
+    hv.buf = r.z;
+    hv.row = r.z == 0 ? a.colp : a.act + (size_t)(r.z - 1) * (size_t)a.nnz;
+    hv.s0 = s;
+    hv.s1 = s + a.split[v];
+    return hv;
+}
+
+// Entry q of the active row (segment 0 first).
+__device__ __forceinline__ int hv_at(const HeavyView& hv, int q) {
+    return hv.row[q < hv.pa ? hv.s0 + q : hv.s1 + (q - hv.pa)];
+}
+
+// Committed colour c (c = minus the state word) of an entry that stays in the
+// active row: not committed (c < 0) or beyond the bitmap.
+__device__ __forceinline__ bool hv_keep(int c) { return c < 0 || c > 64 + kFFBits; }
+
+// Dirty heavy vertex w: new tentative colour, the per-lane part of its
+// counter and of the preceding-dirty flag, the later neighbours' counter
+// updates (as inc_a_eval), and the compaction of its active row.
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, int w, int s, int old, int lig,
+                                            uint64_t* red, int* shc, unsigned* bm, int* cc, int* now_out,
+                                            int* cnt_out, bool* dlow_out) {
+    S* st = static_cast<S*>(a.st);
+    const unsigned* bits = dbits(a, k);
+    const int cs = cset(k);
+    const HeavyView hv = heavy_view(a, w, s);
+    const int len = hv.pa + hv.la;
+    unsigned* F = a.hF + (size_t)hv.h * kFW;
+
+    // pass 1: forbidden colours (starting from the dropped ones) and the
+    // number of entries that stay
+    for (int i = lig; i < kFFWords; i += GS) bm[i] = hv.buf ? F[2 + i] : 0u;
+    uint64_t m = 0;
+    if (hv.buf && lig == 0) m = (uint64_t)F[0] | ((uint64_t)F[1] << 32);
+    group_sync<GS>();
+    int keep = 0;
+    for (int q0 = lig; q0 < len; q0 += 4 * GS) {
+        int x[4], c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = q0 + j * GS;
+            x[j] = q < len ? hv_at(hv, q) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? -(int)st[x[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned lo = (unsigned)(c[j] - 1), hi = (unsigned)(c[j] - 65);
+            if (lo < 64u) m |= 1ull << lo;
+            else if (hi < (unsigned)kFFBits) atomicOr(&bm[hi >> 5], 1u << (hi & 31));
+            keep += x[j] >= 0 && hv_keep(c[j]);
+        }
+    }
+    if constexpr (GS == kBlock) {
+        m = group_or<kWave>(m);
+        keep = group_sum<kWave>(keep);
+        if (__lane_id() == 0) {
+            red[threadIdx.x / kWave] = m;
+            shc[threadIdx.x / kWave] = keep;
+        }
+        __syncthreads();  // also completes the bitmap
+        m = red[0] | red[1] | red[2] | red[3];
+        keep = shc[0] + shc[1] + shc[2] + shc[3];
+        __syncthreads();
+    } else {
+        m = group_or<GS>(m);
+        keep = group_sum<GS>(keep);
+        group_sync<GS>();
+    }
+    int pos = 0x7fffffff;
+    if (~m) {
+        pos = __builtin_ctzll(~m) - 64;
+    } else {
+        for (int i = lig; i < kFFWords; i += GS) {
+            const unsigned z = ~bm[i];
+            if (z) {
+                pos = min(pos, i * 32 + __builtin_ctz(z));
+                break;
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) pos = min(pos, __shfl_xor(pos, o));
+        if constexpr (GS == kBlock) {
+            if (__lane_id() == 0) shc[threadIdx.x / kWave] = pos;
+            __syncthreads();
+            pos = min(min(shc[0], shc[1]), min(shc[2], shc[3]));
+        }
+    }
+    const bool compact = keep * 4 <= len * 3;
+    if (compact) {
+        if (lig == 0) {
+            F[0] = (unsigned)m;
+            F[1] = (unsigned)(m >> 32);
+        }
+        for (int i = lig; i < kFFWords; i += GS) F[2 + i] = bm[i];
+    }
+    group_sync<GS>();  // bitmap, red and shc free again
+    int now = pos == 0x7fffffff ? 0 : 65 + pos;
+    // every colour up to 64 + kFFBits taken: 64-colour windows above, over
+    // the active row (colours there are never dropped)
+    for (int base = 65 + kFFBits; now == 0; base += 64) {
+        uint64_t wm = 0;
+        for (int q = lig; q < len; q += GS) {
+            const unsigned c = (unsigned)(-(int)st[hv_at(hv, q)] - base);
+            if (c < 64u) wm |= 1ull << c;
+        }
+        if constexpr (GS == kBlock) {
+            wm = group_or<kWave>(wm);
+            if (__lane_id() == 0) red[threadIdx.x / kWave] = wm;
+            __syncthreads();
+            wm = red[0] | red[1] | red[2] | red[3];
+            __syncthreads();
+        } else {
+            wm = group_or<GS>(wm);
+        }
+        if (~wm) now = base + __builtin_ctzll(~wm);
+    }
+
+    // pass 2: counters, and the kept entries into the other buffer (any
+    // order within a segment: positions from ballots)
+    const int dbuf = hv.buf == 1 ? 2 : 1;
+    int* dst = a.act + (size_t)(dbuf - 1) * (size_t)a.nnz;
+    int n0 = 0, n1 = 0;
+    if constexpr (GS == kBlock) {
+        if (compact) {
+            if (threadIdx.x == 0) {
+                cc[0] = 0;
+                cc[1] = 0;
+            }
+            __syncthreads();
+        }
+    }
+    int cnt = 0;
+    bool dlow = false;
+    for (int qb = 0; qb < len; qb += 4 * GS) {
+        int x[4], sx[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = qb + lig + j * GS;
+            x[j] = q < len ? hv_at(hv, q) : w;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sx[j] = st[x[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = qb + lig + j * GS;
+            const bool ok = q < len;
+            const bool cand = ok && inc_a_eval(a, bits, k, w, q, hv.pa, now, old, x[j], sx[j], &cnt, &dlow);
+            stage_append_lookup(a, stg, cand, x[j], cs);
+            if (compact) {
+                const bool kp = ok && hv_keep(-sx[j]);
+                const bool pre = q < hv.pa;
+                const unsigned long long m0 = __ballot(kp && pre), m1 = __ballot(kp && !pre);
+                int b0, b1;
+                if constexpr (GS == kBlock) {
+                    int t0 = 0, t1 = 0;
+                    if (__lane_id() == 0) {
+                        if (m0) t0 = atomicAdd(&cc[0], __popcll(m0));
+                        if (m1) t1 = atomicAdd(&cc[1], __popcll(m1));
+                    }
+                    b0 = __shfl(t0, 0);
+                    b1 = __shfl(t1, 0);
+                } else {
+                    b0 = n0;
+                    b1 = n1;
+                    n0 += __popcll(m0);
+                    n1 += __popcll(m1);
+                }
+                const unsigned long long lt = __lanemask_lt();
+                if (kp) dst[pre ? hv.s0 + b0 + __popcll(m0 & lt) : hv.s1 + b1 + __popcll(m1 & lt)] = x[j];
+            }
+        }
+    }
+    if (compact) {
+        if constexpr (GS == kBlock) {
+            __syncthreads();
+            if (threadIdx.x == 0) a.hrow[hv.h] = make_int4(cc[0], cc[1], dbuf, 0);
+        } else {
+            if (lig == 0) a.hrow[hv.h] = make_int4(n0, n1, dbuf, 0);
+        }
+    }
+    *now_out = now;
+    *cnt_out = cnt;
+    *dlow_out = dlow;
+}
+
 // Second pass over a row too long for the register cache: re-gather.
 template <int STRIDE, typename S>
 __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, const S* __restrict__ st,
@@ -733,14 +975,28 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, co
 // workgroup, with LDS for the reductions).  Returns via the stage: w itself
 // to the k_inc_b list or, when its count is final and 0, to the candidates.
 template <int GS, typename S>
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg, int lig,
+                                             int now, int cnt, bool dlow, int* shc, long long* dedges);
+
+template <int GS, typename S>
 __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* stgb, int k, int w, int lig,
-                                             uint64_t* red, int* shc, unsigned* ffbm, long long* dedges) {
+                                             uint64_t* red, int* shc, unsigned* ffbm, int* cc, long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
     const int cs = cset(k);
     const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
-    const int lim = s + a.split[w];
     const int old = st[w];
+    if constexpr (GS == kBlock || GS == kWave) {
+        if (e - s > kHeavyDeg) {
+            unsigned* bm = GS == kBlock ? ffbm : ffbm + (threadIdx.x / kWave) * kFFWords;
+            int now, cnt;
+            bool dlow;
+            inc_a_heavy<GS, S>(a, stg, k, w, s, old, lig, red, shc, bm, cc, &now, &cnt, &dlow);
+            inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, lig, now, cnt, dlow, shc, dedges);
+            return;
+        }
+    }
+    const int lim = s + a.split[w];
     const bool cached = (e - s) <= kCache * GS;
     int xs[kCache], sv[kCache];
     if (cached) {
@@ -796,6 +1052,16 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
+    inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, lig, now, cnt, dlow, shc, dedges);
+}
+
+// Group totals of the counter and the preceding-dirty flag; state, counter
+// and list appends of dirty vertex w.
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg, int lig,
+                                             int now, int cnt, bool dlow, int* shc, long long* dedges) {
+    S* st = static_cast<S*>(a.st);
+    const int cs = cset(k);
     int dl = dlow ? 1 : 0;
     if constexpr (GS == kBlock) {
         cnt = group_sum<kWave>(cnt);
@@ -816,13 +1082,13 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
     if (lig == 0) {
         st[w] = (S)now;
         a.conf[w] = cnt;
-        *dedges += e - s;
+        *dedges += deg;
         to_b = dl > 0;
         cand = !to_b && cnt == 0 && (atomicExch(&a.cflag[w], k) != k);
     }
     if (GS == kBlock && threadIdx.x >= kWave) return;
-    stage_append(a, stgb, to_b, w, e - s, kSetB);
-    stage_append(a, stg, cand, w, e - s, cs);
+    stage_append(a, stgb, to_b, w, deg, kSetB);
+    stage_append(a, stg, cand, w, deg, cs);
 }
 
 template <int GS, typename S>
@@ -831,7 +1097,7 @@ __device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, Stage* st
     constexpr int CV = kBlock / GS;
     const int lig = threadIdx.x & (GS - 1);
     const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, ffbm, dedges);
+    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, ffbm, nullptr, dedges);
 }
 
 // Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
@@ -843,6 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     __shared__ Stage stg;
     __shared__ Stage stgb;
     __shared__ unsigned ffbm[(kBlock / kWave) * kFFWords];
+    __shared__ int cc[2];
     if (blockIdx.x == 0 && threadIdx.x == 0 && k - 1 < kMaxLog) {
         long long nd = 0;
         for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dlist(k)][b];
@@ -870,7 +1137,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     stage_init(&stgb);
     long long dedges = 0;
 #define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, ffbm, &dedges)
-#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, &dedges)
+#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, &dedges)
 #define A_AFTER()                                \
     {                                            \
         stage_maybe_flush(a, &stg, cset(k));     \
@@ -888,7 +1155,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
 // Round k, kernel B: for dirty vertices with preceding dirty neighbours, add
 // those holding the same (final) new colour to the counter.
 template <int STRIDE, typename S>
-__device__ __forceinline__ int inc_b_count(const Args& a, const S* __restrict__ st,
+__device__ __forceinline__ int inc_b_count(const int* __restrict__ row, const S* __restrict__ st,
                                            const unsigned* __restrict__ bits, int w, int start, int lim, int now) {
     int c = 0;
     for (int p0 = start; p0 < lim; p0 += 4 * STRIDE) {
@@ -897,7 +1164,7 @@ __device__ __forceinline__ int inc_b_count(const Args& a, const S* __restrict__ 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int p = p0 + j * STRIDE;
-            x[j] = p < lim ? a.colp[p] : w;
+            x[j] = p < lim ? row[p] : w;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) d[j] = (p0 + j * STRIDE < lim) && is_dirty(bits, x[j]);
@@ -921,7 +1188,16 @@ __device__ __forceinline__ void inc_b_chunk(const Args& a, Stage* stg, int k, co
         const int s = a.row_ptr[w];
         deg = a.row_ptr[w + 1] - s;
         const int now = st[w];
-        int c = inc_b_count<GS, S>(a, st, dbits(a, k), w, s + lig, s + a.split[w], now);
+        const int* row = a.colp;
+        int lim = s + a.split[w];
+        if constexpr (GS == kWave) {
+            if (deg > kHeavyDeg) {  // preceding segment of the active row
+                const HeavyView hv = heavy_view(a, w, s);
+                row = hv.row;
+                lim = s + hv.pa;
+            }
+        }
+        int c = inc_b_count<GS, S>(row, st, dbits(a, k), w, s + lig, lim, now);
         c = group_sum<GS>(c);
         if (lig == 0) {
             const int tot = a.conf[w] + c;
@@ -937,7 +1213,14 @@ __device__ __forceinline__ void inc_b_block(const Args& a, Stage* stg, int k, in
     const S* st = static_cast<const S*>(a.st);
     const int s = a.row_ptr[w], deg = a.row_ptr[w + 1] - s;
     const int now = st[w];
-    int c = inc_b_count<kBlock, S>(a, st, dbits(a, k), w, s + (int)threadIdx.x, s + a.split[w], now);
+    const int* row = a.colp;
+    int lim = s + a.split[w];
+    if (deg > kHeavyDeg) {  // preceding segment of the active row
+        const HeavyView hv = heavy_view(a, w, s);
+        row = hv.row;
+        lim = s + hv.pa;
+    }
+    int c = inc_b_count<kBlock, S>(row, st, dbits(a, k), w, s + (int)threadIdx.x, lim, now);
     c = group_sum<kWave>(c);
     if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -989,8 +1272,8 @@ __device__ __forceinline__ bool inc_c_eval(const Args& a, unsigned* __restrict__
 }
 
 template <int STRIDE, typename S>
-__device__ __forceinline__ void inc_c_row(const Args& a, Stage* stg, const S* __restrict__ st, int k, int v, int t,
-                                          int start, int e) {
+__device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__ row, Stage* stg,
+                                          const S* __restrict__ st, int k, int v, int t, int start, int e) {
     unsigned* nbits = dbits(a, k + 1);
     const int ds = dlist(k + 1);
     for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
@@ -998,7 +1281,7 @@ __device__ __forceinline__ void inc_c_row(const Args& a, Stage* stg, const S* __
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int p = p0 + j * STRIDE;
-            u[j] = p < e ? a.colp[p] : v;
+            u[j] = p < e ? row[p] : v;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) su[j] = st[u[j]];
@@ -1022,7 +1305,17 @@ __device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, co
         const int t = st[v];
         if (a.conf[v] == 0 && t > 0) {
             const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
-            inc_c_row<GS, S>(a, stg, st, k, v, t, s + a.split[v] + lig, e);
+            const int* row = a.colp;
+            int start = s + a.split[v], end = e;
+            if constexpr (GS == kWave) {
+                if (e - s > kHeavyDeg) {  // later segment of the active row
+                    const HeavyView hv = heavy_view(a, v, s);
+                    row = hv.row;
+                    start = hv.s1;
+                    end = hv.s1 + hv.la;
+                }
+            }
+            inc_c_row<GS, S>(a, row, stg, st, k, v, t, start + lig, end);
             if (lig == 0) {
                 a.color[v] = t;
                 st[v] = (S)(-t);
@@ -1041,7 +1334,15 @@ __device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, in
     const int t = st[v];
     if (a.conf[v] != 0 || t <= 0) return;  // block-uniform: only this block writes them in this kernel
     const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
-    inc_c_row<kBlock, S>(a, stg, st, k, v, t, s + a.split[v] + (int)threadIdx.x, e);
+    const int* row = a.colp;
+    int start = s + a.split[v], end = e;
+    if (e - s > kHeavyDeg) {  // later segment of the active row
+        const HeavyView hv = heavy_view(a, v, s);
+        row = hv.row;
+        start = hv.s1;
+        end = hv.s1 + hv.la;
+    }
+    inc_c_row<kBlock, S>(a, row, stg, st, k, v, t, start + (int)threadIdx.x, end);
     __syncthreads();  // every thread has read st[v] before it is overwritten
     if (threadIdx.x == 0) {
         a.color[v] = t;
@@ -1341,7 +1642,7 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, dbits, colp, total;
+    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, dbits, colp, hid, hrow, hF, act, total;
 };
 
 Layout layout(int32_t n, int64_t nnz) {
@@ -1359,6 +1660,12 @@ Layout layout(int32_t n, int64_t nnz) {
     L.lists = off; off += align_up(vn * kSets * kBins);
     L.dbits = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.colp = off;  off += align_up(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    // rows of degree > kHeavyDeg: at most nnz / (kHeavyDeg + 1) of them
+    const size_t nh = (size_t)(nnz > 0 ? nnz : 0) / (kHeavyDeg + 1) + 1;
+    L.hid = off;   off += align_up(vn);
+    L.hrow = off;  off += align_up(sizeof(int4) * nh);
+    L.hF = off;    off += align_up(sizeof(uint32_t) * kFW * nh);
+    L.act = off;   off += align_up(sizeof(int32_t) * 2 * (size_t)(nnz > 0 ? nnz : 1));
     L.total = off;
     return L;
 }
@@ -1589,6 +1896,11 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     a.ctl = ctl;
     a.log = log;
     a.cfg = current_bins();
+    a.hid = reinterpret_cast<int*>(base + Lw.hid);
+    a.hrow = reinterpret_cast<int4*>(base + Lw.hrow);
+    a.hF = reinterpret_cast<unsigned*>(base + Lw.hF);
+    a.act = reinterpret_cast<int*>(base + Lw.act);
+    a.nnz = nnz;
 
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
     if (!natural) {
