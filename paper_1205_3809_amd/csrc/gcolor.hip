@@ -1116,7 +1116,9 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
         a.log[kLogW * (k - 1) + 0] = 0;
         a.log[kLogW * (k - 1) + 1] = 0;
         a.log[kLogW * (k - 1) + 2] = nd;
-        a.log[kLogW * (k - 1) + 3] = 0;
+        // field 3 (dirty degree sum) collects this kernel's blocks: it was
+        // cleared by the previous kernel, not here, so that no block adds
+        // before block 0 clears it
     }
     const ChunkMap m = make_map(a.ctl, dlist(k));
     int nprev = 0;
@@ -1359,11 +1361,13 @@ __device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, in
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
     __shared__ Stage stg;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int b = 0; b < 8; ++b) {
             a.ctl->cnt[cset(k + 1)][b] = 0;
             a.ctl->cnt[kSetB][b] = 0;
         }
+        if (k < kMaxLog) a.log[kLogW * k + 3] = 0;  // round k+1's dirty degree sum
+    }
     const ChunkMap m = make_map(a.ctl, cset(k));
     if ((int)blockIdx.x >= m.total) return;
     stage_init(&stg);

@@ -124,6 +124,36 @@ def test_long_dirty_rows(m, leaves):
     assert col[-1] == m + 1
 
 
+def dirty_model(g, key=None):
+    """Per round: number and degree sum of the worklist vertices whose
+    tentative colour differs from the previous round's (the vertices the
+    incremental engine must revisit), from the set-notation simulation."""
+    adj = oracle.adjacency(g.row_ptr, g.col_idx)
+    deg = g.degrees()
+    prev, out = {}, []
+
+    def trace(k, U, tent, R, color):
+        moved = [v for v in U if k > 1 and tent[v] != prev[v]]
+        out.append((len(moved), int(sum(deg[v] for v in moved))))
+        prev.update(tent)
+
+    oracle.spec_sim_py(adj, None if key is None else [int(x) for x in key], trace=trace)
+    return out
+
+
+@pytest.mark.parametrize("case", ["rmat12", "rmat12-perm", "clique+hub"])
+def test_dirty_statistics(case):
+    """The incremental engine's per-round dirty count and dirty degree sum
+    (heavy rows included: R-MAT scale 12 with the training skew has rows above
+    512, the hub row has 670) equal the model's."""
+    g = clique_plus_hub(70, 600) if case == "clique+hub" else rmat(12, 16, (0.57, 0.19, 0.19), 4)
+    key = graphgen.random_priority(g.n, 3) if case.endswith("perm") else None
+    col, st = gpu_color(g, key)
+    want = dirty_model(g, key)
+    got = [(int(d[1]), int(d[2])) for d in st.detail]
+    assert got == want
+
+
 @pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (32767, 5), (32768, 5), (70000, 123)])
 def test_star_hubs(n, center):
     """A centre of degree up to 70k runs on the workgroup-per-vertex bin."""
