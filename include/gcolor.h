@@ -84,7 +84,10 @@ typedef struct gcolor_stats {
 /* Per-round record written to round_log (host memory) by color_graph_ex:
  * round index (1-based), |U_k| (worklist size), E_k (sum of degrees over
  * U_k), vertices committed in the round, and for the incremental engine the
- * number of dirty vertices (tentative colour changed) and their degree sum. */
+ * number of dirty vertices (tentative colour changed), their degree sum, and
+ * the row entries its dirty pass read for them (equal to the degree sum
+ * except for rows longer than 512 entries, which are read without the
+ * neighbours already committed). */
 typedef struct gcolor_round {
     int64_t round;
     int64_t worklist;
@@ -92,6 +95,7 @@ typedef struct gcolor_round {
     int64_t committed;
     int64_t dirty;
     int64_t dirty_edges;
+    int64_t scanned;
 } gcolor_round_t;
 
 /* Bytes of device workspace color_graph_ex needs for a graph of this size. */

@@ -34,7 +34,8 @@ class _Stats(ctypes.Structure):
 
 class _Round(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int64), ("worklist", ctypes.c_int64), ("edge_work", ctypes.c_int64),
-                ("committed", ctypes.c_int64), ("dirty", ctypes.c_int64), ("dirty_edges", ctypes.c_int64)]
+                ("committed", ctypes.c_int64), ("dirty", ctypes.c_int64), ("dirty_edges", ctypes.c_int64),
+                ("scanned", ctypes.c_int64)]
 
 
 class Stats(NamedTuple):
@@ -42,7 +43,8 @@ class Stats(NamedTuple):
     num_colors: int
     edge_work: int
     round_log: List[Tuple[int, int, int]]  # (k, |U_k|, E_k)
-    detail: List[Tuple[int, int, int]]     # (committed, dirty, dirty degree sum) per round
+    # per round: (committed, dirty, dirty degree sum, row entries the dirty pass read)
+    detail: List[Tuple[int, int, int, int]]
 
 
 def library_path() -> str:
@@ -181,7 +183,8 @@ def color_graph_ex(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optio
     if logbuf is not None:
         for i in range(min(st.rounds, max_log)):
             log.append((int(logbuf[i].round), int(logbuf[i].worklist), int(logbuf[i].edge_work)))
-            detail.append((int(logbuf[i].committed), int(logbuf[i].dirty), int(logbuf[i].dirty_edges)))
+            detail.append((int(logbuf[i].committed), int(logbuf[i].dirty), int(logbuf[i].dirty_edges),
+                           int(logbuf[i].scanned)))
     return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), log, detail)
 
 

@@ -50,6 +50,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <mutex>
 #include <vector>
 
@@ -68,7 +69,7 @@ constexpr int kFW = 132;
 constexpr int kBins = 5;
 constexpr int kSets = 6;          // list sets (plain: 0,1 worklist ping-pong; incremental: see below)
 constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
-constexpr int kLogW = 4;          // int64 words per logged round
+constexpr int kLogW = 5;          // int64 words per logged round
 
 // Vertices covered by one block-sized chunk of each bin.
 __host__ __device__ constexpr int chunk_vertices(int b) {
@@ -107,8 +108,7 @@ struct Args {
     int* __restrict__ split;       // entries at the front of each row that precede the vertex
     int* __restrict__ color;       // the caller's colors_out: 0 until committed
     int* __restrict__ tent;        // (plain) tentative colour
-    void* st;                      // (incremental) state words, int16_t or int32_t
-    void* stold;                   // (incremental) tentative colour before this round's change
+    void* st;                      // (incremental) state words, int8_t, int16_t or int32_t
     int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
     int* __restrict__ stamp;       // (incremental) round of last dirty mark
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
@@ -508,8 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
 // ===========================================================================
 // Incremental engine (rounds k = 1, 2, ...; round 1 needs only k_inc_c)
 //
-// One signed state word per vertex, S = int16_t when every colour fits
-// (max degree + 1 <= 32767), else int32_t:
+// One signed state word per vertex: S = int8_t for rounds 1..127 (no
+// colour can exceed the round number), then int16_t, or int32_t when max
+// degree + 1 exceeds 32767:
 //   st[v] > 0   v is uncoloured, st[v] is its tentative colour
 //   st[v] < 0   v is committed with colour -st[v]
 // so a single gather of a neighbour's word answers every question a kernel
@@ -782,7 +783,7 @@ __device__ __forceinline__ bool hv_keep(int c) { return c < 0 || c > 64 + kFFBit
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, int w, int s, int old, int lig,
                                             uint64_t* red, int* shc, unsigned* bm, int* cc, int* now_out,
-                                            int* cnt_out, bool* dlow_out) {
+                                            int* cnt_out, bool* dlow_out, int* len_out) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
     const int cs = cset(k);
@@ -945,6 +946,7 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
     *now_out = now;
     *cnt_out = cnt;
     *dlow_out = dlow;
+    *len_out = len;
 }
 
 // Second pass over a row too long for the register cache: re-gather.
@@ -975,8 +977,9 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, co
 // workgroup, with LDS for the reductions).  Returns via the stage: w itself
 // to the k_inc_b list or, when its count is final and 0, to the candidates.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg, int lig,
-                                             int now, int cnt, bool dlow, int* shc, long long* dedges);
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg,
+                                             int scanned, int lig, int now, int cnt, bool dlow, int* shc,
+                                             long long* dedges);
 
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* stgb, int k, int w, int lig,
@@ -991,8 +994,9 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
             unsigned* bm = GS == kBlock ? ffbm : ffbm + (threadIdx.x / kWave) * kFFWords;
             int now, cnt;
             bool dlow;
-            inc_a_heavy<GS, S>(a, stg, k, w, s, old, lig, red, shc, bm, cc, &now, &cnt, &dlow);
-            inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, lig, now, cnt, dlow, shc, dedges);
+            int len;
+            inc_a_heavy<GS, S>(a, stg, k, w, s, old, lig, red, shc, bm, cc, &now, &cnt, &dlow, &len);
+            inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, len, lig, now, cnt, dlow, shc, dedges);
             return;
         }
     }
@@ -1052,14 +1056,15 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
-    inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, lig, now, cnt, dlow, shc, dedges);
+    inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, e - s, lig, now, cnt, dlow, shc, dedges);
 }
 
 // Group totals of the counter and the preceding-dirty flag; state, counter
 // and list appends of dirty vertex w.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg, int lig,
-                                             int now, int cnt, bool dlow, int* shc, long long* dedges) {
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg,
+                                             int scanned, int lig, int now, int cnt, bool dlow, int* shc,
+                                             long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const int cs = cset(k);
     int dl = dlow ? 1 : 0;
@@ -1082,7 +1087,8 @@ __device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* s
     if (lig == 0) {
         st[w] = (S)now;
         a.conf[w] = cnt;
-        *dedges += deg;
+        dedges[0] += deg;
+        dedges[1] += scanned;
         to_b = dl > 0;
         cand = !to_b && cnt == 0 && (atomicExch(&a.cflag[w], k) != k);
     }
@@ -1116,9 +1122,9 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
         a.log[kLogW * (k - 1) + 0] = 0;
         a.log[kLogW * (k - 1) + 1] = 0;
         a.log[kLogW * (k - 1) + 2] = nd;
-        // field 3 (dirty degree sum) collects this kernel's blocks: it was
-        // cleared by the previous kernel, not here, so that no block adds
-        // before block 0 clears it
+        // fields 3 and 4 (dirty degree sum, entries scanned) collect this
+        // kernel's blocks: the previous kernel cleared them, not block 0 here,
+        // so that no block adds before they are cleared
     }
     const ChunkMap m = make_map(a.ctl, dlist(k));
     int nprev = 0;
@@ -1137,9 +1143,9 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     }
     stage_init(&stg);
     stage_init(&stgb);
-    long long dedges = 0;
-#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, ffbm, &dedges)
-#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, &dedges)
+    long long dedges[2] = {0, 0};  // degree sum and scanned entries of the dirty rows
+#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, ffbm, dedges)
+#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, dedges)
 #define A_AFTER()                                \
     {                                            \
         stage_maybe_flush(a, &stg, cset(k));     \
@@ -1151,7 +1157,10 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
 #undef A_AFTER
     stage_flush(a, &stg, cset(k));
     stage_flush(a, &stgb, kSetB);
-    if (k - 1 < kMaxLog) block_add_log(dedges, &a.log[kLogW * (k - 1) + 3]);
+    if (k - 1 < kMaxLog) {
+        block_add_log(dedges[0], &a.log[kLogW * (k - 1) + 3]);
+        block_add_log(dedges[1], &a.log[kLogW * (k - 1) + 4]);
+    }
 }
 
 // Round k, kernel B: for dirty vertices with preceding dirty neighbours, add
@@ -1366,7 +1375,10 @@ __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
             a.ctl->cnt[cset(k + 1)][b] = 0;
             a.ctl->cnt[kSetB][b] = 0;
         }
-        if (k < kMaxLog) a.log[kLogW * k + 3] = 0;  // round k+1's dirty degree sum
+        if (k < kMaxLog) {  // round k+1's dirty degree sum and scanned entries
+            a.log[kLogW * k + 3] = 0;
+            a.log[kLogW * k + 4] = 0;
+        }
     }
     const ChunkMap m = make_map(a.ctl, cset(k));
     if ((int)blockIdx.x >= m.total) return;
@@ -1830,13 +1842,17 @@ int run_plain(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hi
     }
 }
 
+// Rounds *k, *k + 1, ... up to round `last` (inclusive) or the end, in
+// batches between host checks; *done when the next round's dirty list is
+// empty (every vertex committed).
 template <typename S>
-int run_incremental(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st) {
-    GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid, kBlock, 0, st>>>(a, 1); }));
-    int k = 2;
-    int batch = 4;
-    for (;;) {
-        for (int j = 0; j < batch; ++j, ++k) {
+int inc_rounds(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st, int* kio, int last,
+               int* batch, bool* done) {
+    int k = *kio;
+    *done = false;
+    while (k <= last) {
+        const int nb = std::min(*batch, last - k + 1);
+        for (int j = 0; j < nb; ++j, ++k) {
             GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid, kBlock, 0, st>>>(a, k); }));
             GC_CHECK(L(kProfIncB, [&] { k_inc_b<S><<<grid, kBlock, 0, st>>>(a, k); }));
             GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid, kBlock, 0, st>>>(a, k); }));
@@ -1844,9 +1860,55 @@ int run_incremental(const Args& a, int64_t n, int grid, Launcher& L, int32_t* ho
         // dirty list of the next round k: empty exactly when every vertex is committed
         GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dlist(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
         GC_CHECK(hipStreamSynchronize(st));
-        if (sum_counts(host) == 0) break;
+        *kio = k;
+        if (sum_counts(host) == 0) {
+            *done = true;
+            return GCOLOR_OK;
+        }
         if (k > n + 64) return GCOLOR_EROUNDS;
-        batch = std::min(batch * 2, 16);
+        *batch = std::min(*batch * 2, 16);
+    }
+    return GCOLOR_OK;
+}
+
+// Widen the state words into another slot (int8 -> int16 / int32).
+template <typename D>
+__global__ __launch_bounds__(kBlock) void k_widen(int n, const int8_t* __restrict__ src, D* __restrict__ dst) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) dst[v] = (D)src[v];
+}
+
+// A tentative colour is at most one above the largest committed colour, and
+// that grows by at most one per round, so every colour of rounds 1..127 fits
+// a signed byte: the engine starts with 8-bit state words (half the bytes of
+// the gathers that dominate every kernel) and, if round 128 is reached,
+// widens them to 16 bits (32 when max degree + 1 exceeds 32767).
+int run_incremental(Args a, int64_t n, int vgrid, int grid, bool natural, void* wide_slot, Launcher& L,
+                    int32_t* host, hipStream_t st) {
+    constexpr int kLast8 = 127;
+    k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    GC_CHECK(hipGetLastError());
+    GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid, kBlock, 0, st>>>(a, 1); }));
+    int k = 2, batch = 4;
+    bool done = false;
+    int rc = inc_rounds<int8_t>(a, n, grid, L, host, st, &k, kLast8, &batch, &done);
+    if (rc) return rc;
+    if (!done) {
+        k_maxdeg<<<vgrid, kBlock, 0, st>>>((int)n, a.row_ptr, a.ctl);
+        GC_CHECK(hipGetLastError());
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->maxdeg, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        const int8_t* narrow = static_cast<const int8_t*>(a.st);
+        a.st = wide_slot;
+        if (host[0] + 1 <= 32767) {
+            k_widen<int16_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int16_t*>(wide_slot));
+            GC_CHECK(hipGetLastError());
+            rc = inc_rounds<int16_t>(a, n, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+        } else {
+            k_widen<int32_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int32_t*>(wide_slot));
+            GC_CHECK(hipGetLastError());
+            rc = inc_rounds<int32_t>(a, n, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+        }
+        if (rc) return rc;
     }
     unsigned long long committed = 0;
     GC_CHECK(hipMemcpyAsync(&committed, &a.ctl->committed, sizeof(committed), hipMemcpyDeviceToHost, st));
@@ -1890,7 +1952,6 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     a.tent = reinterpret_cast<int*>(base + Lw.tent);
     // the incremental engine's state words share the plain engine's slots
     a.st = base + Lw.tent;
-    a.stold = base + Lw.told;
     a.conf = reinterpret_cast<int*>(base + Lw.conf);
     a.stamp = reinterpret_cast<int*>(base + Lw.stamp);
     a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
@@ -1928,20 +1989,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         }
         rc = run_plain(a, n, grid, L, host, st);
     } else {
-        // colours are at most max degree + 1: 16-bit state words when that fits
-        k_maxdeg<<<vgrid, kBlock, 0, st>>>(n, row_ptr, ctl);
-        GC_CHECK(hipGetLastError());
-        GC_CHECK(hipMemcpyAsync(host, &ctl->maxdeg, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GC_CHECK(hipStreamSynchronize(st));
-        if (host[0] + 1 <= 32767) {
-            k_inc_seed<int16_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
-            GC_CHECK(hipGetLastError());
-            rc = run_incremental<int16_t>(a, n, grid, L, host, st);
-        } else {
-            k_inc_seed<int32_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
-            GC_CHECK(hipGetLastError());
-            rc = run_incremental<int32_t>(a, n, grid, L, host, st);
-        }
+        rc = run_incremental(a, n, vgrid, grid, natural, base + Lw.told, L, host, st);
     }
     if (rc) return rc;
 
@@ -1970,7 +2018,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
                                     st));
         GC_CHECK(hipStreamSynchronize(st));
         // per round: worklist size and its degree sum
-        std::vector<long long> U(nl), E(nl), C(nl, 0), D(nl, 0), DE(nl, 0);
+        std::vector<long long> U(nl), E(nl), C(nl, 0), D(nl, 0), DE(nl, 0), SC(nl, 0);
         if (plain) {
             for (int r = 0; r < nl; ++r) {
                 U[r] = hl[kLogW * r];
@@ -1985,6 +2033,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
                 C[r] = hl[kLogW * r];
                 D[r] = hl[kLogW * r + 2];
                 DE[r] = hl[kLogW * r + 3];
+                SC[r] = hl[kLogW * r + 4];
                 u -= hl[kLogW * r];
                 e -= hl[kLogW * r + 1];
             }
@@ -2006,6 +2055,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
                 round_log[r].committed = C[r];
                 round_log[r].dirty = D[r];
                 round_log[r].dirty_edges = DE[r];
+                round_log[r].scanned = SC[r];
             }
         }
     }

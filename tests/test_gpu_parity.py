@@ -116,10 +116,12 @@ def clique_plus_hub(m, leaves):
     return graphgen.from_pairs(hub + 1, src, dst)
 
 
-@pytest.mark.parametrize("m,leaves", [(70, 600), (300, 600), (300, 3000), (130, 9000)])
+@pytest.mark.parametrize("m,leaves", [(70, 600), (300, 600), (300, 3000), (130, 9000), (200, 40000)])
 def test_long_dirty_rows(m, leaves):
     """Long rows that stay dirty for many rounds (wave and workgroup tiers,
-    colours past the first 64-colour window), against the oracle."""
+    colours past the first 64-colour window), against the oracle.  Past
+    round 127 the state words widen: to 16 bits, and to 32 bits for the hub
+    of degree 40200."""
     col, st = check(clique_plus_hub(m, leaves), label="clique+hub")
     assert col[-1] == m + 1
 
@@ -152,6 +154,13 @@ def test_dirty_statistics(case):
     want = dirty_model(g, key)
     got = [(int(d[1]), int(d[2])) for d in st.detail]
     assert got == want
+    # entries read: the whole row, except rows above 512 entries once part of
+    # them has committed
+    assert all(d[3] <= d[2] for d in st.detail)
+    if g.degrees().max() <= 512:
+        assert all(d[3] == d[2] for d in st.detail)
+    else:
+        assert sum(d[3] for d in st.detail) < sum(d[2] for d in st.detail)
 
 
 @pytest.mark.parametrize("n,center", [(3000, 0), (3000, 2999), (20000, 0), (20000, 19999), (32767, 5), (32768, 5), (70000, 123)])
