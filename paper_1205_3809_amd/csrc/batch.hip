@@ -15,8 +15,12 @@
 // Lanes: groups of 8 lanes per vertex (the stencil and geometric graphs of a
 // batch have degrees of a few to a few tens), eight row entries per lane
 // kept in registers between the first-fit and the counter pass; longer rows
-// are re-gathered.  Per-graph start/end times come from the constant-rate
-// wall clock.  No host synchronisation and no allocation happen inside the
+// are re-gathered.
+//
+// Graphs of at most nl vertices (nl is set per launch from the batch's mean
+// graph size, at most 65536) and maximum degree at most 126 keep their
+// per-vertex state in LDS (see color_one_lds); the others use global memory.
+// Per-graph start/end times come from the constant-rate wall clock.  No host synchronisation and no allocation happen inside the
 // call, so it can be captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
@@ -62,6 +66,7 @@ struct BArgs {
     BCtl* ctl;
     long long* __restrict__ ticks;     // [2G] start, end (wall clock) or null
     int* __restrict__ rounds;          // [G] or null
+    int nl;                            // vertex capacity of the LDS path (0: off)
 };
 
 struct GView {
@@ -241,13 +246,236 @@ __device__ void phase_c(const GView& g, int* cnt, int k, int v, int lig) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// LDS-resident rounds.  A graph of at most nl vertices whose maximum degree is
+// at most kLdsMaxDeg keeps its per-vertex state in LDS: signed-byte state
+// words (colours are at most max degree + 1 <= 127), byte counters packed
+// four to a word and changed with 32-bit atomics (a counter never exceeds the
+// degree, so +1 never carries into the next byte, and -1 is only applied to a
+// positive counter), two dirty bitmaps alternating by round (the first mark
+// of a vertex is the one that sets its bit) and a bitmap of this round's
+// candidates.  Row data, split points, colours and lists stay in global
+// memory.  A round's chain of dependent accesses then reaches global memory a
+// few times instead of about twenty, and it is that chain, slowed by the load
+// the rest of the batch puts on the memory system, which paces the long runs
+// of small rounds (natural-order grids: ~1250 rounds of ~50 vertices).
+constexpr int kLdsMaxDeg = 126;
+
+struct LView {
+    int n, nw;
+    const int* rp;
+    const int* col;
+    const int* split;
+    int* color;
+    int* lbase;
+    int64_t lstride;
+    int8_t* st;    // LDS: state words
+    unsigned* cf;  // LDS: byte counters, four per word
+    unsigned* db;  // LDS: dirty bitmaps of rounds with even / odd index
+    unsigned* cb;  // LDS: candidates pushed in this round
+    __device__ __forceinline__ int* L(int i) const { return lbase + (int64_t)i * lstride; }
+    __device__ __forceinline__ unsigned* dbits(int k) const { return db + (k & 1) * nw; }
+};
+
+__device__ __forceinline__ unsigned vbit(int v) { return 1u << (v & 31); }
+
+__device__ __forceinline__ int lconf(const LView& g, int v) { return (g.cf[v >> 2] >> ((v & 3) * 8)) & 0xff; }
+
+// Adds d to v's byte counter; returns the byte before.
+__device__ __forceinline__ int lconf_add(const LView& g, int v, int d) {
+    const unsigned sh = (unsigned)(v & 3) * 8u;
+    const unsigned old = atomicAdd(&g.cf[v >> 2], (unsigned)d << sh);
+    return (int)((old >> sh) & 0xffu);
+}
+
+// First push of candidate x in this round.
+__device__ __forceinline__ bool lcand(const LView& g, int x) { return !(atomicOr(&g.cb[x >> 5], vbit(x)) & vbit(x)); }
+
+__device__ __forceinline__ void lpush(const LView& g, int* cnt, int list, int v) {
+    const int slot = atomicAdd(&cnt[list], 1);
+    g.L(list)[slot] = v;
+}
+
+// Entry x (word sx) of dirty vertex w, as eval_dirty with LDS state.
+__device__ __forceinline__ void eval_l(const LView& g, int* cnt, const unsigned* bits, int k, int w, bool pre, int now,
+                                       int old, int x, int sx, int* c, bool* dlow) {
+    if (pre) {
+        if (dirty_bit(bits, x)) *dlow = true;
+        else *c += (sx == now);
+    } else if (x != w && (sx == now || sx == old) && !dirty_bit(bits, x)) {
+        if (sx == now) lconf_add(g, x, 1);
+        else if (lconf_add(g, x, -1) == 1 && lcand(g, x)) lpush(g, cnt, cl(k), x);
+    }
+}
+
+__device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
+    const unsigned* bits = g.dbits(k);
+    const int s = g.rp[w], e = g.rp[w + 1];
+    const int lim = s + g.split[w];
+    const int old = g.st[w];
+    const bool cached = (e - s) <= kCache * kG;
+    int xs[kCache], sv[kCache];
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) {
+            const int p = s + lig + j * kG;
+            xs[j] = p < e ? g.col[p] : w;
+        }
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) sv[j] = g.st[xs[j]];
+    }
+    int now = 0;
+    for (int base = 1;; base += 64) {
+        uint64_t m = 0;
+        if (cached) {
+#pragma unroll
+            for (int j = 0; j < kCache; ++j) {
+                const unsigned c = (unsigned)(-sv[j] - base);
+                if (c < 64u) m |= 1ull << c;
+            }
+        } else {
+            for (int p = s + lig; p < e; p += kG) {
+                const unsigned c = (unsigned)(-(int)g.st[g.col[p]] - base);
+                if (c < 64u) m |= 1ull << c;
+            }
+        }
+        m = gor<kG>(m);
+        if (~m) {
+            now = base + __builtin_ctzll(~m);
+            break;
+        }
+    }
+    int c = 0;
+    bool dlow = false;
+    if (cached) {
+#pragma unroll
+        for (int j = 0; j < kCache; ++j) {
+            const int p = s + lig + j * kG;
+            if (p < e) eval_l(g, cnt, bits, k, w, p < lim, now, old, xs[j], sv[j], &c, &dlow);
+        }
+    } else {
+        for (int p = s + lig; p < e; p += kG) {
+            const int x = g.col[p];
+            eval_l(g, cnt, bits, k, w, p < lim, now, old, x, g.st[x], &c, &dlow);
+        }
+    }
+    c = gsum<kG>(c);
+    const int d = gsum<kG>(dlow ? 1 : 0);
+    if (lig == 0) {
+        g.st[w] = (int8_t)now;
+        // w is dirty, so no other group changes its counter in this phase
+        lconf_add(g, w, c - lconf(g, w));
+        if (d > 0) lpush(g, cnt, 5, w);
+        else if (c == 0 && lcand(g, w)) lpush(g, cnt, cl(k), w);
+    }
+}
+
+__device__ void phase_b_l(const LView& g, int* cnt, int k, int w, int lig) {
+    const unsigned* bits = g.dbits(k);
+    const int s = g.rp[w];
+    const int lim = s + g.split[w];
+    const int now = g.st[w];
+    int c = 0;
+    for (int p = s + lig; p < lim; p += kG) {
+        const int x = g.col[p];
+        if (dirty_bit(bits, x)) c += ((int)g.st[x] == now);
+    }
+    c = gsum<kG>(c);
+    if (lig == 0) {
+        const int t = lconf_add(g, w, c) + c;
+        if (t == 0 && lcand(g, w)) lpush(g, cnt, cl(k), w);
+    }
+}
+
+__device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
+    if (lig == 0) atomicAnd(&g.cb[v >> 5], ~vbit(v));  // the candidate bit is free for the next round
+    const int t = g.st[v];
+    if (lconf(g, v) != 0 || t <= 0) return;  // uniform over the group
+    unsigned* nbits = g.dbits(k + 1);
+    const int s = g.rp[v], e = g.rp[v + 1];
+    for (int p = s + g.split[v] + lig; p < e; p += kG) {
+        const int u = g.col[p];
+        if (u == v || (int)g.st[u] != t) continue;
+        if (atomicOr(&nbits[u >> 5], vbit(u)) & vbit(u)) continue;  // marked already
+        lpush(g, cnt, dl(k + 1), u);
+    }
+    if (lig == 0) {
+        g.color[v] = t;
+        g.st[v] = (int8_t)(-t);
+    }
+}
+
+// Rounds of graph gi (n vertices, split points set) with LDS state; the
+// caller has cleared cnt[].
+__device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt, unsigned char* lds, int& kout) {
+    const int tid = threadIdx.x;
+    LView g;
+    g.n = gg.n;
+    g.nw = (a.nl + 31) >> 5;
+    g.rp = gg.rp;
+    g.col = gg.col;
+    g.split = gg.split;
+    g.color = gg.color;
+    g.lbase = gg.lbase;
+    g.lstride = gg.lstride;
+    g.st = reinterpret_cast<int8_t*>(lds);
+    g.cf = reinterpret_cast<unsigned*>(lds + a.nl);
+    g.db = reinterpret_cast<unsigned*>(lds + 2 * (size_t)a.nl);
+    g.cb = g.db + 2 * g.nw;
+    const int nw = (g.n + 31) >> 5;
+    for (int i = tid; i < nw; i += kB) {
+        g.db[i] = 0u;
+        g.db[g.nw + i] = 0u;
+        g.cb[i] = 0u;
+    }
+    unsigned char* cfb = reinterpret_cast<unsigned char*>(g.cf);
+    for (int v = tid; v < g.n; v += kB) {
+        const int sp = g.split[v];
+        g.st[v] = 1;
+        cfb[v] = (unsigned char)sp;
+        if (sp == 0) lpush(g, cnt, cl(1), v);
+    }
+    if (tid == 0) cnt[dl(2)] = 0;
+    __syncthreads();
+    const int grp = tid / kG, lig = tid & (kG - 1);
+    int k = 1;
+    for (;; ++k) {
+        if (k > 1) {
+            const int nd = cnt[dl(k)];
+            if (nd == 0) break;
+            // round k-1's bitmap becomes round k+1's: clear the words of its
+            // dirty vertices (every bit set in it belongs to one of them)
+            const int np = cnt[dl(k - 1)];
+            for (int i = tid; i < np; i += kB) g.dbits(k - 1)[g.L(dl(k - 1))[i] >> 5] = 0u;
+            if (tid == 0) {
+                cnt[cl(k)] = 0;
+                cnt[5] = 0;
+                cnt[dl(k + 1)] = 0;
+            }
+            __syncthreads();
+            for (int i = grp; i < nd; i += kPerIt) phase_a_l(g, cnt, k, g.L(dl(k))[i], lig);
+            __syncthreads();
+            const int nb = cnt[5];
+            if (nb > 0) {
+                for (int i = grp; i < nb; i += kPerIt) phase_b_l(g, cnt, k, g.L(5)[i], lig);
+                __syncthreads();
+            }
+        }
+        const int nc = cnt[cl(k)];
+        for (int i = grp; i < nc; i += kPerIt) phase_c_l(g, cnt, k, g.L(cl(k))[i], lig);
+        __syncthreads();
+    }
+    kout = k;
+}
+
 __device__ __forceinline__ bool precedes(const uint32_t* key, int w, uint32_t kv, int v) {
     const uint32_t kw = key[w];
     return kw < kv || (kw == kv && w < v);
 }
 
 // Colour graph gi with the whole workgroup.
-__device__ void color_one(const BArgs& a, int gi, int* cnt) {
+__device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, int* shmax) {
     const int tid = threadIdx.x;
     const int64_t vo = a.vtx_off[gi], eo = a.edge_off[gi];
     const int n = (int)(a.vtx_off[gi + 1] - vo);
@@ -279,8 +507,21 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt) {
     const uint32_t* key = a.key ? a.key + vo : nullptr;
     const int* raw = a.col_idx + eo;
 
+    // LDS path when the graph fits and every colour and counter fits a byte
+    bool use_lds = false;
+    if (a.nl > 0 && n <= a.nl) {
+        int md = 0;
+        for (int v = tid; v < n; v += kB) md = max(md, g.rp[v + 1] - g.rp[v]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) md = max(md, __shfl_xor(md, o));
+        if ((tid & 63) == 0) shmax[tid >> 6] = md;
+        __syncthreads();
+        use_lds = max(max(shmax[0], shmax[1]), max(shmax[2], shmax[3])) <= kLdsMaxDeg;
+        __syncthreads();
+    }
     if (tid < 8) cnt[tid] = 0;
-    for (int i = tid; i < 3 * nw; i += kB) g.bits(i / nw)[i % nw] = 0u;
+    if (!use_lds)
+        for (int i = tid; i < 3 * nw; i += kB) g.bits(i / nw)[i % nw] = 0u;
     __syncthreads();
     // set-up: split points (reordered rows with a priority), round-1 state
     for (int v = tid; v < n; v += kB) {
@@ -308,6 +549,7 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt) {
             sp = nlo;
         }
         g.split[v] = sp;
+        if (use_lds) continue;
         g.st[v] = 1;
         g.conf[v] = sp;
         g.stamp[v] = 0;
@@ -315,6 +557,16 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt) {
         if (sp == 0) push(g, cnt, cl(1), v);
     }
     __syncthreads();
+    if (use_lds) {
+        int k = 1;
+        color_one_lds(a, g, gi, cnt, lds, k);
+        if (tid == 0) {
+            if (a.rounds) a.rounds[gi] = k - 1;
+            if (a.ticks) a.ticks[2 * gi + 1] = wall_clock64();
+        }
+        __syncthreads();
+        return;
+    }
     const int grp = tid / kG, lig = tid & (kG - 1);
     int k = 1;
     for (;; ++k) {
@@ -351,7 +603,9 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt) {
 }
 
 __global__ __launch_bounds__(kB) void k_batch(BArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];  // 19 nl / 8 bytes for the LDS path
     __shared__ int cnt[8];
+    __shared__ int shmax[kB / 64];
     __shared__ int slot;
     for (;;) {
         if (threadIdx.x == 0) slot = atomicAdd(&a.ctl->queue, 1);
@@ -359,7 +613,7 @@ __global__ __launch_bounds__(kB) void k_batch(BArgs a) {
         const int q = slot;
         __syncthreads();
         if (q >= a.G) return;  // every wave of the workgroup leaves here once the queue is drained
-        color_one(a, a.order[q], cnt);
+        color_one(a, a.order[q], cnt, lds, shmax);
     }
 }
 
@@ -475,8 +729,21 @@ int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     k_batch_order<<<1, 1024, 0, st>>>(num_graphs, edge_off, a.order, a.ctl);
     if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
+    // LDS path capacity: eight times the mean graph size, at least 1024 and at
+    // most 65536 vertices (19/8 bytes per vertex: 152 KiB at the top); the
+    // largest graphs of a batch of small ones then take the global path
+    // rather than lowering every workgroup's occupancy.
+    int64_t nl = total_vertices > 0 ? (8 * total_vertices + num_graphs - 1) / num_graphs : 0;
+    nl = std::max<int64_t>(nl, 1024);
+    nl = std::min<int64_t>(nl, 65536);
+    nl = (nl + 31) & ~(int64_t)31;
+    a.nl = (int)nl;
+    const size_t lds_bytes = (size_t)19 * (size_t)nl / 8;
+    if (hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+        hipSuccess)
+        return GCOLOR_EHIP;
     const int grid = std::min(num_graphs, cus * 8);
-    k_batch<<<grid, kB, 0, st>>>(a);
+    k_batch<<<grid, kB, lds_bytes, st>>>(a);
     if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
     return GCOLOR_OK;
 }

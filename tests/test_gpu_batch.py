@@ -72,7 +72,10 @@ def mixed_graphs(seed, count=40, lo=4.0, hi=10.0):
     specs = graphgen.batch_specs(count, seed, lo, hi)
     gs = [graphgen.batch_graph(s) for s in specs]
     # structural edge cases in the same batch
+    # (K_127: degree 126 and colour 127, the largest that keeps its state in
+    # LDS; K_128 and the star take the global-memory path)
     gs += [graphgen.empty(1), graphgen.empty(0), graphgen.empty(5), graphgen.complete(70),
+           graphgen.complete(127), graphgen.complete(128),
            graphgen.star(3000, 0), graphgen.path(130), graphgen.cycle(64),
            graphgen.rmat(10, 8, (0.55, 0.1, 0.1), 4), graphgen.uniform(700, 3000, 2)]
     return gs
