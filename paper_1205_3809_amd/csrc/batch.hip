@@ -33,9 +33,7 @@
 
 namespace {
 
-constexpr int kB = 256;       // threads per workgroup
 constexpr int kG = 8;         // lanes per vertex
-constexpr int kPerIt = kB / kG;
 constexpr int kCache = 8;     // row entries per lane kept in registers
 constexpr int kSortMax = 8192;
 
@@ -408,7 +406,9 @@ __device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
 
 // Rounds of graph gi (n vertices, split points set) with LDS state; the
 // caller has cleared cnt[].
+template <int B>
 __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt, unsigned char* lds, int& kout) {
+    constexpr int kPerIt = B / kG;
     const int tid = threadIdx.x;
     LView g;
     g.n = gg.n;
@@ -424,13 +424,13 @@ __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt,
     g.db = reinterpret_cast<unsigned*>(lds + 2 * (size_t)a.nl);
     g.cb = g.db + 2 * g.nw;
     const int nw = (g.n + 31) >> 5;
-    for (int i = tid; i < nw; i += kB) {
+    for (int i = tid; i < nw; i += B) {
         g.db[i] = 0u;
         g.db[g.nw + i] = 0u;
         g.cb[i] = 0u;
     }
     unsigned char* cfb = reinterpret_cast<unsigned char*>(g.cf);
-    for (int v = tid; v < g.n; v += kB) {
+    for (int v = tid; v < g.n; v += B) {
         const int sp = g.split[v];
         g.st[v] = 1;
         cfb[v] = (unsigned char)sp;
@@ -447,7 +447,7 @@ __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt,
             // round k-1's bitmap becomes round k+1's: clear the words of its
             // dirty vertices (every bit set in it belongs to one of them)
             const int np = cnt[dl(k - 1)];
-            for (int i = tid; i < np; i += kB) g.dbits(k - 1)[g.L(dl(k - 1))[i] >> 5] = 0u;
+            for (int i = tid; i < np; i += B) g.dbits(k - 1)[g.L(dl(k - 1))[i] >> 5] = 0u;
             if (tid == 0) {
                 cnt[cl(k)] = 0;
                 cnt[5] = 0;
@@ -474,8 +474,10 @@ __device__ __forceinline__ bool precedes(const uint32_t* key, int w, uint32_t kv
     return kw < kv || (kw == kv && w < v);
 }
 
-// Colour graph gi with the whole workgroup.
+// Colour graph gi with the whole workgroup (B threads).
+template <int B>
 __device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, int* shmax) {
+    constexpr int kPerIt = B / kG;
     const int tid = threadIdx.x;
     const int64_t vo = a.vtx_off[gi], eo = a.edge_off[gi];
     const int n = (int)(a.vtx_off[gi + 1] - vo);
@@ -511,20 +513,22 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, 
     bool use_lds = false;
     if (a.nl > 0 && n <= a.nl) {
         int md = 0;
-        for (int v = tid; v < n; v += kB) md = max(md, g.rp[v + 1] - g.rp[v]);
+        for (int v = tid; v < n; v += B) md = max(md, g.rp[v + 1] - g.rp[v]);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) md = max(md, __shfl_xor(md, o));
         if ((tid & 63) == 0) shmax[tid >> 6] = md;
         __syncthreads();
-        use_lds = max(max(shmax[0], shmax[1]), max(shmax[2], shmax[3])) <= kLdsMaxDeg;
+        md = 0;
+        for (int i = 0; i < B / 64; ++i) md = max(md, shmax[i]);
+        use_lds = md <= kLdsMaxDeg;
         __syncthreads();
     }
     if (tid < 8) cnt[tid] = 0;
     if (!use_lds)
-        for (int i = tid; i < 3 * nw; i += kB) g.bits(i / nw)[i % nw] = 0u;
+        for (int i = tid; i < 3 * nw; i += B) g.bits(i / nw)[i % nw] = 0u;
     __syncthreads();
     // set-up: split points (reordered rows with a priority), round-1 state
-    for (int v = tid; v < n; v += kB) {
+    for (int v = tid; v < n; v += B) {
         const int s = g.rp[v], e = g.rp[v + 1];
         int sp;
         if (!key) {
@@ -559,7 +563,7 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, 
     __syncthreads();
     if (use_lds) {
         int k = 1;
-        color_one_lds(a, g, gi, cnt, lds, k);
+        color_one_lds<B>(a, g, gi, cnt, lds, k);
         if (tid == 0) {
             if (a.rounds) a.rounds[gi] = k - 1;
             if (a.ticks) a.ticks[2 * gi + 1] = wall_clock64();
@@ -575,7 +579,7 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, 
             const int nd = cnt[dl(k)];
             if (nd == 0) break;
             const int np = cnt[dl(k - 1)];
-            for (int i = tid; i < np; i += kB) g.bits(dl(k - 1))[g.L(dl(k - 1))[i] >> 5] = 0u;
+            for (int i = tid; i < np; i += B) g.bits(dl(k - 1))[g.L(dl(k - 1))[i] >> 5] = 0u;
             __syncthreads();
             if (tid == 0) {
                 cnt[cl(k)] = 0;
@@ -602,10 +606,14 @@ __device__ void color_one(const BArgs& a, int gi, int* cnt, unsigned char* lds, 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kB) void k_batch(BArgs a) {
+// B threads per workgroup: 1024 when the LDS path's capacity leaves one
+// workgroup per CU anyway (more vertex groups in flight for the large rounds
+// of big graphs), else 256 (several workgroups, graphs, per CU).
+template <int B>
+__global__ __launch_bounds__(B) void k_batch(BArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];  // 19 nl / 8 bytes for the LDS path
     __shared__ int cnt[8];
-    __shared__ int shmax[kB / 64];
+    __shared__ int shmax[B / 64];
     __shared__ int slot;
     for (;;) {
         if (threadIdx.x == 0) slot = atomicAdd(&a.ctl->queue, 1);
@@ -613,7 +621,7 @@ __global__ __launch_bounds__(kB) void k_batch(BArgs a) {
         const int q = slot;
         __syncthreads();
         if (q >= a.G) return;  // every wave of the workgroup leaves here once the queue is drained
-        color_one(a, a.order[q], cnt, lds, shmax);
+        color_one<B>(a, a.order[q], cnt, lds, shmax);
     }
 }
 
@@ -739,11 +747,18 @@ int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_
     nl = (nl + 31) & ~(int64_t)31;
     a.nl = (int)nl;
     const size_t lds_bytes = (size_t)19 * (size_t)nl / 8;
-    if (hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
-        hipSuccess)
-        return GCOLOR_EHIP;
     const int grid = std::min(num_graphs, cus * 8);
-    k_batch<<<grid, kB, lds_bytes, st>>>(a);
+    if (nl >= 16384) {
+        if (hipFuncSetAttribute((const void*)k_batch<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_bytes) != hipSuccess)
+            return GCOLOR_EHIP;
+        k_batch<1024><<<grid, 1024, lds_bytes, st>>>(a);
+    } else {
+        if (hipFuncSetAttribute((const void*)k_batch<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_bytes) != hipSuccess)
+            return GCOLOR_EHIP;
+        k_batch<256><<<grid, 256, lds_bytes, st>>>(a);
+    }
     if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
     return GCOLOR_OK;
 }
