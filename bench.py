@@ -51,6 +51,28 @@ def make_graph(name):
     return graphgen.uniform(p["n"], p["samples"], p["seed"])
 
 
+def apply_tuning(args, name, search):
+    """Launch parameters for this workload: searched and stored with
+    --autotune, else read from the package's tuning table (library defaults
+    with --no-tuning or when the table has no entry).  Returns what was used."""
+    from paper_1205_3809_amd import autotune
+    import paper_1205_3809_amd as gc
+
+    if args.autotune:
+        entry = search()
+        autotune.save(autotune.TABLE, name, entry)
+        log("autotune %s: %s (%.3f ms, from %.3f ms)" % (name, {k: v for k, v in entry.items()
+                                                              if k not in ("trials", "ms", "start_ms")},
+                                                       entry["ms"], entry["start_ms"]))
+    elif not args.no_tuning:
+        entry = autotune.apply(autotune.TABLE, name)
+    else:
+        entry = None
+    if entry is None:
+        return {"source": "library defaults", "single": gc.get_tuning(), "batch": list(gc.get_batch_tuning())}
+    return {"source": "autotuner table", **{k: v for k, v in entry.items() if k not in ("trials",)}}
+
+
 def kernel_source_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1205_3809_amd", "csrc")
@@ -136,6 +158,10 @@ def main():
     ap.add_argument("--engine", default="incremental", choices=["incremental", "plain"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the launch parameters for this workload, store them in the package's "
+                         "tuning table, then measure with them")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the tuning table (library defaults)")
     args = ap.parse_args()
 
     if WORKLOADS[args.workload][0] == "batch" and args.gpus == 1:
@@ -169,6 +195,8 @@ def main():
     pr = None if key is None else torch.from_numpy(key.view(np.int32)).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
+    tuning = apply_tuning(args, "%s-%s" % (args.workload, args.order),
+                          lambda: gc.autotune.tune_single(rp, ci, pr, log=log))
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
@@ -304,7 +332,7 @@ def main():
 
     p = WORKLOADS[args.workload][1]
     config = {"workload": "%s-%s" % (args.workload, args.order), "engine": args.engine,
-              "n": g.n, "nnz": g.nnz, "edges": g.edges}
+              "n": g.n, "nnz": g.nnz, "edges": g.edges, "tuning": tuning}
     config.update({k: v for k, v in p.items()})
     res = {
         "metric": "edges colored/sec + % HBM peak at R-MAT s24; colors vs serial greedy",
@@ -355,6 +383,8 @@ def bench_batch(args):
     ws = torch.empty(gc.batch_workspace_bytes(G, V, nnz), dtype=torch.uint8, device=dev)
     ticks = torch.zeros(2 * G, dtype=torch.int64, device=dev)
     rounds = torch.zeros(G, dtype=torch.int32, device=dev)
+    tuning = apply_tuning(args, args.workload,
+                          lambda: gc.autotune.tune_batch(vo, eo, rp, ci, V, nnz, log=log))
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -402,7 +432,8 @@ def bench_batch(args):
         "value": round(edges / (ms / 1000.0), 1), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "graphs": G, "vertices": V, "nnz": nnz, "edges": edges},
+        "config": {"workload": args.workload, "graphs": G, "vertices": V, "nnz": nnz, "edges": edges,
+                   "tuning": tuning},
         "per_graph_ms": {"service_p50": round(float(np.percentile(service_ms, 50)), 4),
                          "service_p99": round(float(np.percentile(service_ms, 99)), 4),
                          "completion_p50": round(float(np.percentile(done_ms, 50)), 4),

@@ -126,10 +126,25 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
  * largest degrees of bins 0..3 (one lane, 4 lanes, 16 lanes and one
  * wavefront per vertex); larger degrees take a workgroup per vertex.  Must be
  * non-decreasing.  blocks_per_cu (1..64, 0 = keep) sizes the phase grids.
- * NULL bin_limits keeps the current limits.  Results never depend on tuning.
+ * NULL bin_limits keeps the current limits.  Defaults: {8, 32, 128, 2048}
+ * and 4.  Results never depend on tuning.  The autotuner (Python package,
+ * autotune.py) searches these per configuration.
  */
 int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu);
 int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
+
+/*
+ * Batch tuning (process-wide, applies to later color_graph_batch calls).
+ * block_threads: threads per workgroup, 256 or 1024, or 0 for the default
+ * (1024 when the LDS capacity below is at least 16384 vertices, else 256).
+ * lds_factor (1..64): the LDS path's vertex capacity is lds_factor times the
+ * batch's mean graph size, at least 1024 and at most lds_max_vertices
+ * (0..65536; 0 disables the LDS path, every graph then keeps its state in
+ * global memory).  Errors: GCOLOR_EINVAL for values out of range.  Results
+ * never depend on tuning.
+ */
+int gcolor_set_batch_tuning(int32_t block_threads, int32_t lds_factor, int32_t lds_max_vertices);
+int gcolor_get_batch_tuning(int32_t* block_threads, int32_t* lds_factor, int32_t* lds_max_vertices);
 
 /*
  * Kernel timing with HIP events recorded around every phase launch.

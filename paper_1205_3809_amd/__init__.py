@@ -23,6 +23,8 @@ from ._binding import (  # noqa: F401
     PROF_INC_B,
     PROF_INC_C,
     get_tuning,
+    get_batch_tuning,
+    set_batch_tuning,
     profile,
     profile_read,
     raw_library,
@@ -31,3 +33,14 @@ from ._binding import (  # noqa: F401
     color_graph_batch,
     wall_clock_khz,
 )
+
+from . import autotune  # noqa: E402,F401
+
+# A tuning table chosen by the autotuner can be applied at import:
+# GCOLOR_TUNING=<table.json>:<config name>.
+import os as _os
+
+if _os.environ.get("GCOLOR_TUNING"):
+    from .autotune import apply_from_env as _apply_from_env
+
+    _apply_from_env(_os.environ["GCOLOR_TUNING"])

@@ -72,6 +72,9 @@ def _load():
     lib.gcolor_set_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.gcolor_set_tuning.restype = ctypes.c_int
     lib.gcolor_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.gcolor_set_batch_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gcolor_set_batch_tuning.restype = ctypes.c_int
+    lib.gcolor_get_batch_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.gcolor_get_tuning.restype = ctypes.c_int
     lib.gcolor_profile.argtypes = [ctypes.c_int32]
     lib.gcolor_profile.restype = ctypes.c_int
@@ -223,6 +226,21 @@ def get_tuning():
     bpc = ctypes.c_int32()
     _lib.gcolor_get_tuning(arr, ctypes.byref(bpc))
     return list(arr), int(bpc.value)
+
+
+def set_batch_tuning(block_threads: int = 0, lds_factor: int = 8, lds_max_vertices: int = 65536) -> None:
+    """Threads per workgroup (0 = automatic, 256, 1024) and the LDS path's
+    vertex capacity (lds_factor x mean graph size, capped at lds_max_vertices;
+    0 disables it) of color_graph_batch; speed only, never the colouring."""
+    rc = _lib.gcolor_set_batch_tuning(int(block_threads), int(lds_factor), int(lds_max_vertices))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_set_batch_tuning")
+
+
+def get_batch_tuning():
+    v = [ctypes.c_int32() for _ in range(3)]
+    _lib.gcolor_get_batch_tuning(*[ctypes.byref(x) for x in v])
+    return tuple(int(x.value) for x in v)
 
 
 PROF_PHASE1 = 0   # plain engine: tentative colouring

@@ -28,6 +28,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "gcolor.h"
 
@@ -663,6 +664,11 @@ __global__ __launch_bounds__(1024) void k_batch_order(int G, const int64_t* __re
 
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Process-wide batch tuning (gcolor_set_batch_tuning).
+std::atomic<int> g_block_threads{0};
+std::atomic<int> g_lds_factor{8};
+std::atomic<int> g_lds_max{65536};
+
 struct BLayout {
     size_t ctl, order, st, conf, stamp, cflag, split, lists, bits, colp, total;
     int64_t nbw;
@@ -737,18 +743,24 @@ int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     k_batch_order<<<1, 1024, 0, st>>>(num_graphs, edge_off, a.order, a.ctl);
     if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
-    // LDS path capacity: eight times the mean graph size, at least 1024 and at
-    // most 65536 vertices (19/8 bytes per vertex: 152 KiB at the top); the
-    // largest graphs of a batch of small ones then take the global path
-    // rather than lowering every workgroup's occupancy.
-    int64_t nl = total_vertices > 0 ? (8 * total_vertices + num_graphs - 1) / num_graphs : 0;
-    nl = std::max<int64_t>(nl, 1024);
-    nl = std::min<int64_t>(nl, 65536);
-    nl = (nl + 31) & ~(int64_t)31;
+    // LDS path capacity: lds_factor (default 8) times the mean graph size, at
+    // least 1024 and at most lds_max (default 65536) vertices (19/8 bytes per
+    // vertex: 152 KiB at the top); the largest graphs of a batch of small ones
+    // then take the global path rather than lowering every workgroup's
+    // occupancy.
+    const int lds_max = g_lds_max.load(), lds_factor = g_lds_factor.load();
+    int64_t nl = 0;
+    if (lds_max > 0) {
+        nl = total_vertices > 0 ? (lds_factor * total_vertices + num_graphs - 1) / num_graphs : 0;
+        nl = std::max<int64_t>(nl, 1024);
+        nl = std::min<int64_t>(nl, lds_max);
+        nl = (nl + 31) & ~(int64_t)31;
+    }
     a.nl = (int)nl;
     const size_t lds_bytes = (size_t)19 * (size_t)nl / 8;
     const int grid = std::min(num_graphs, cus * 8);
-    if (nl >= 16384) {
+    const int bt = g_block_threads.load();
+    if (bt == 1024 || (bt == 0 && nl >= 16384)) {
         if (hipFuncSetAttribute((const void*)k_batch<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_bytes) != hipSuccess)
             return GCOLOR_EHIP;
@@ -760,6 +772,22 @@ int color_graph_batch(int32_t num_graphs, int64_t total_vertices, int64_t total_
         k_batch<256><<<grid, 256, lds_bytes, st>>>(a);
     }
     if (hipGetLastError() != hipSuccess) return GCOLOR_EHIP;
+    return GCOLOR_OK;
+}
+
+int gcolor_set_batch_tuning(int32_t block_threads, int32_t lds_factor, int32_t lds_max_vertices) {
+    if (block_threads != 0 && block_threads != 256 && block_threads != 1024) return GCOLOR_EINVAL;
+    if (lds_factor < 1 || lds_factor > 64 || lds_max_vertices < 0 || lds_max_vertices > 65536) return GCOLOR_EINVAL;
+    g_block_threads.store(block_threads);
+    g_lds_factor.store(lds_factor);
+    g_lds_max.store(lds_max_vertices);
+    return GCOLOR_OK;
+}
+
+int gcolor_get_batch_tuning(int32_t* block_threads, int32_t* lds_factor, int32_t* lds_max_vertices) {
+    if (block_threads) *block_threads = g_block_threads.load();
+    if (lds_factor) *lds_factor = g_lds_factor.load();
+    if (lds_max_vertices) *lds_max_vertices = g_lds_max.load();
     return GCOLOR_OK;
 }
 

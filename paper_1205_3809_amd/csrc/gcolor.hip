@@ -1697,7 +1697,7 @@ std::vector<DeviceCache> g_dev;
 
 // Process-wide tuning: degree-bin limits and blocks per CU of the grids.
 int g_bins[4] = {8, 32, 128, 2048};
-int g_blocks_per_cu = 8;
+int g_blocks_per_cu = 4;
 
 // Optional per-kernel timing with HIP events recorded around each launch.
 enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfKinds = 5 };

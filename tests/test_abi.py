@@ -96,3 +96,42 @@ def test_tuning_validation():
     assert gc.get_tuning() == ([4, 16, 64, 1024], 4)
     gc.set_tuning(old, bpc)
     assert gc.get_tuning() == (old, bpc)
+
+
+def test_batch_tuning_roundtrip_and_range():
+    import paper_1205_3809_amd as gc
+    old = gc.get_batch_tuning()
+    try:
+        gc.set_batch_tuning(1024, 4, 32768)
+        assert gc.get_batch_tuning() == (1024, 4, 32768)
+        for bad in [(512, 8, 65536), (256, 0, 65536), (256, 65, 65536), (256, 8, 65537), (256, 8, -1)]:
+            with pytest.raises(gc.GColorError):
+                gc.set_batch_tuning(*bad)
+        assert gc.get_batch_tuning() == (1024, 4, 32768)
+    finally:
+        gc.set_batch_tuning(*old)
+
+
+def test_tuning_table_save_and_apply(tmp_path):
+    """The autotuner's table: entries keyed by architecture and name, loaded
+    into the library by apply() (no device needed for this part)."""
+    import paper_1205_3809_amd as gc
+    from paper_1205_3809_amd import autotune
+    path = str(tmp_path / "t.json")
+    s_old, b_old = gc.get_tuning(), gc.get_batch_tuning()
+    try:
+        autotune.save(path, "g1", {"kind": "single", "bin_limits": [4, 16, 64, 1024], "blocks_per_cu": 4},
+                      arch_name="gfx950")
+        autotune.save(path, "b1", {"kind": "batch", "block_threads": 256, "lds_factor": 4,
+                                   "lds_max_vertices": 16384}, arch_name="gfx950")
+        assert autotune.apply(path, "g1", arch_name="gfx950")["blocks_per_cu"] == 4
+        assert gc.get_tuning() == ([4, 16, 64, 1024], 4)
+        autotune.apply(path, "b1", arch_name="gfx950")
+        assert gc.get_batch_tuning() == (256, 4, 16384)
+        assert autotune.apply(path, "missing", arch_name="gfx950") is None
+        assert autotune.apply(path, "g1", arch_name="gfx942") is None
+        with pytest.raises(ValueError):
+            autotune.apply_from_env("no-colon")
+    finally:
+        gc.set_tuning(*s_old)
+        gc.set_batch_tuning(*b_old)

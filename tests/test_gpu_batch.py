@@ -123,3 +123,40 @@ def test_batch_full_size_sampled():
         ref = oracle.spec_sim(g.row_ptr, g.col_idx)
         assert np.array_equal(out[b.vtx_off[i]:b.vtx_off[i + 1]], ref.colors), i
         assert rounds[i] == ref.rounds
+
+
+def test_batch_tuning_does_not_change_colours():
+    """Every batch launch setting (256 or 1024 threads, LDS capacity, LDS path
+    off) gives the oracle's colours."""
+    import paper_1205_3809_amd as gc
+    gs = mixed_graphs(9, count=24) + [graphgen.grid((90, 90), True)]
+    old = gc.get_batch_tuning()
+    try:
+        for t in [(256, 8, 65536), (1024, 8, 65536), (256, 1, 1024), (1024, 64, 65536), (256, 8, 0),
+                  (1024, 8, 0), (0, 2, 16384)]:
+            print("batch tuning", t, flush=True)
+            gc.set_batch_tuning(*t)
+            check_batch(gs)
+    finally:
+        gc.set_batch_tuning(*old)
+
+
+def test_autotuner_searches_keep_colours():
+    """The autotuner's searches run, return their best setting, and check on
+    every trial that the colours do not change (they raise otherwise)."""
+    import torch
+    import paper_1205_3809_amd as gc
+    from paper_1205_3809_amd import autotune
+    s_old, b_old = gc.get_tuning(), gc.get_batch_tuning()
+    try:
+        g = graphgen.rmat(14, 8, (0.55, 0.1, 0.1), 3)
+        rp, ci = dev(g.row_ptr), dev(g.col_idx)
+        e = autotune.tune_single(rp, ci, reps=1, passes=1)
+        assert e["kind"] == "single" and len(e["trials"]) > 5 and e["ms"] <= e["start_ms"]
+        b = graphgen.concat(mixed_graphs(11, count=16))
+        V, E = int(b.vtx_off[-1]), int(b.edge_off[-1])
+        e = autotune.tune_batch(dev(b.vtx_off), dev(b.edge_off), dev(b.row_ptr), dev(b.col_idx), V, E, reps=1)
+        assert e["kind"] == "batch" and e["ms"] <= e["start_ms"]
+    finally:
+        gc.set_tuning(*s_old)
+        gc.set_batch_tuning(*b_old)
