@@ -11,7 +11,8 @@
 //   k_feat_stats   per-feature sum and sum of squares of log1p(feature)
 //   k_mlp_forward  score per vertex: x = (log1p(f) - mean) / std,
 //                  y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, weights in BF16
-//                  (stored as bf16 bits), FP32 accumulation
+//                  (stored as bf16 bits), FP32 accumulation; the 64x64 layer
+//                  on matrix cores (v_mfma_f32_16x16x32_bf16)
 //   k_mlp_backward per-workgroup partial gradients of the mean squared error
 //                  over a minibatch (same BF16 weights in the forward part)
 //   k_grad_reduce  sums the partials
@@ -85,13 +86,17 @@ __device__ __forceinline__ uint64_t wedge_hash(uint64_t seed, int v, int i) {
 }
 
 // Sample i of vertex v (degree d >= 2, row at s): 1 if the wedge closes.
+// The edge test searches the shorter of the two endpoints' rows (the
+// adjacency is symmetric, so either answers it).
 __device__ __forceinline__ int wedge_closed(const int* __restrict__ row_ptr, const int* __restrict__ col, int v,
                                             int s, int d, int i, uint64_t seed) {
     const uint64_t h = wedge_hash(seed, v, i);
     const int a = (int)((h & 0xffffffffULL) % (uint64_t)d);
     int b = (int)((h >> 32) % (uint64_t)(d - 1));
     if (b >= a) b += 1;
-    return has_edge(row_ptr, col, col[s + a], col[s + b]) ? 1 : 0;
+    const int wa = col[s + a], wb = col[s + b];
+    const int da = row_ptr[wa + 1] - row_ptr[wa], db = row_ptr[wb + 1] - row_ptr[wb];
+    return (db < da ? has_edge(row_ptr, col, wb, wa) : has_edge(row_ptr, col, wa, wb)) ? 1 : 0;
 }
 
 __device__ __forceinline__ void write_features(float* __restrict__ out, int v, int d, int mn, int mx, long long sum,
@@ -107,20 +112,30 @@ __device__ __forceinline__ void write_features(float* __restrict__ out, int v, i
     f[7] = (float)h;
 }
 
-// One vertex of degree < kFeatHeavy per group of GS lanes.
+// One vertex of degree < kFeatHeavy per group of GS lanes; the neighbour
+// degrees (at most kFeatHeavy / GS per lane) stay in registers.
 template <int GS>
 __device__ void features_light(int v, int s, int e, int lig, const int* __restrict__ row_ptr,
                                const int* __restrict__ col, uint64_t seed, float* __restrict__ out) {
+    constexpr int kPer = kFeatHeavy / GS;
     const int d = e - s;
+    int dv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int p = s + lig + j * GS;
+        dv[j] = p < e ? col[p] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) dv[j] = dv[j] >= 0 ? row_ptr[dv[j] + 1] - row_ptr[dv[j]] : -1;
     int mn = 0x7fffffff, mx = 0;
     long long sum = 0;
-    for (int p = s + lig; p < e; p += GS) {
-        const int w = col[p];
-        const int dw = row_ptr[w + 1] - row_ptr[w];
-        mn = min(mn, dw);
-        mx = max(mx, dw);
-        sum += dw;
-    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (dv[j] >= 0) {
+            mn = min(mn, dv[j]);
+            mx = max(mx, dv[j]);
+            sum += dv[j];
+        }
 #pragma unroll
     for (int o = GS / 2; o > 0; o >>= 1) {
         mn = min(mn, __shfl_xor(mn, o, GS));
@@ -129,11 +144,13 @@ __device__ void features_light(int v, int s, int e, int lig, const int* __restri
     }
     // h-index: largest h with at least h neighbours of degree >= h; h is at
     // most min(d, max neighbour degree); binary search over that range
+    // (absent entries hold -1 and never count)
     int lo = 0, hi = min(d, mx);
     while (lo < hi) {
         const int h = (lo + hi + 1) >> 1;
         int c = 0;
-        for (int p = s + lig; p < e; p += GS) c += (row_ptr[col[p] + 1] - row_ptr[col[p]]) >= h;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) c += dv[j] >= h;
 #pragma unroll
         for (int o = GS / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, GS);
         if (c >= h) lo = h;
@@ -390,32 +407,101 @@ __device__ __forceinline__ void normalise(const MlpLds* m, const float* __restri
     for (int f = 0; f < kF; ++f) x[f] = (log1pf(raw[f]) - m->mean[f]) * m->istd[f];
 }
 
-// One vertex per thread.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Forward pass, 16 vertices per wave at a time.  The 64x64 layer is a
+// (16 x 64) x (64 x 64) product per tile on v_mfma_f32_16x16x32_bf16: lane l
+// holds, of an A tile (16 x 32), row l % 16 and k = 8 (l / 16) + 0..7; of a B
+// tile (32 x 16), column l % 16 and the same k; of the 16 x 16 result, rows
+// 4 (l / 16) + 0..3 of column l % 16.  So each lane computes, in FP32, the 16
+// first-layer units of its vertex (l % 16) that its A fragments need, and the
+// W2 fragments (BF16, as stored) stay in registers for the whole launch.
+// The first-layer activations enter the product as two BF16 parts (the
+// rounded value and the rounding remainder), so the product keeps ~16
+// significant bits of them; accumulation is FP32.
 __global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, const float* __restrict__ feat,
                                                      const float* __restrict__ master,
                                                      const uint16_t* __restrict__ wbf,
                                                      const float* __restrict__ norm, float* __restrict__ score) {
     __shared__ MlpLds m;
     load_mlp(&m, master, wbf, norm);
-    for (int64_t v = blockIdx.x * 256LL + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
-        float x[kF], a1[kH];
-        normalise(&m, feat + v * kF, x);
+    const int l = threadIdx.x & 63;
+    const int row = l & 15, kq = l >> 4;
+    // W2 fragments: B[k][c] = W2[c][k] for output tile t (c = 16 t + row) and
+    // k-step s (k = 32 s + 8 kq + e): eight consecutive BF16 of row c of W2
+    bf16x8 bw[4][2];
 #pragma unroll
-        for (int i = 0; i < kH; ++i) {
-            float z = m.b1[i];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int f = 0; f < kF; ++f) z = fmaf(m.w1[i * kF + f], x[f], z);
-            a1[i] = fmaxf(z, 0.0f);
+        for (int ks = 0; ks < 2; ++ks)
+            bw[t][ks] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4*>(wbf + kPW2 + (16 * t + row) * kH + 32 * ks + 8 * kq));
+    float w3c[4], b2c[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        w3c[t] = m.w3[16 * t + row];
+        b2c[t] = m.b2[16 * t + row];
+    }
+    const int64_t tiles = (n + 15) >> 4;
+    const int64_t wstride = (int64_t)gridDim.x * (256 / 64);
+    for (int64_t tile = (int64_t)blockIdx.x * (256 / 64) + (threadIdx.x >> 6); tile < tiles; tile += wstride) {
+        // re-read the first-layer weights from LDS each tile rather than
+        // holding the 128 a lane uses in registers (that would leave one
+        // wave per SIMD)
+        __asm__ __volatile__("" ::: "memory");
+        const int64_t v = tile * 16 + row;
+        float raw[kF], x[kF];
+        if (v < n) {
+            const float4 f0 = *reinterpret_cast<const float4*>(feat + v * kF);
+            const float4 f1 = *reinterpret_cast<const float4*>(feat + v * kF + 4);
+            raw[0] = f0.x; raw[1] = f0.y; raw[2] = f0.z; raw[3] = f0.w;
+            raw[4] = f1.x; raw[5] = f1.y; raw[6] = f1.z; raw[7] = f1.w;
+        } else {
+#pragma unroll
+            for (int f = 0; f < kF; ++f) raw[f] = 0.0f;
         }
-        float y = m.b3;
-#pragma unroll 1
-        for (int j = 0; j < kH; ++j) {
-            float z = m.b2[j];
+        normalise(&m, raw, x);
+        // first layer: units j = 32 ks + 8 kq + e of vertex `row`
+        bf16x8 ahi[2], alo[2];
 #pragma unroll
-            for (int i = 0; i < kH; ++i) z = fmaf(m.w2[j * kH + i], a1[i], z);
-            y = fmaf(m.w3[j], fmaxf(z, 0.0f), y);
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = 32 * ks + 8 * kq + e;
+                float z = m.b1[j];
+#pragma unroll
+                for (int f = 0; f < kF; ++f) z = fmaf(m.w1[j * kF + f], x[f], z);
+                const float a = fmaxf(z, 0.0f);
+                const __bf16 hi = (__bf16)a;
+                ahi[ks][e] = hi;
+                alo[ks][e] = (__bf16)(a - (float)hi);
+            }
+        // second layer on matrix cores, third layer on the vector units
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[ks], bw[t][ks], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[ks], bw[t][ks], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[r] = fmaf(w3c[t], fmaxf(acc[r] + b2c[t], 0.0f), part[r]);
         }
-        score[v] = y;
+        // sum over the 16 columns held by the lanes of this quarter-wave
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) part[r] += __shfl_xor(part[r], o, 16);
+        if (row == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t u = tile * 16 + 4 * kq + r;
+                if (u < n) score[u] = part[r] + m.b3;
+            }
+        }
     }
 }
 
@@ -724,7 +810,7 @@ int gcolor_mlp_forward(int64_t n, const float* feat, const float* master, const 
     if (n == 0) return GCOLOR_OK;
     if (!feat || !score) return GCOLOR_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    k_mlp_forward<<<grid_for(n, 256), 256, 0, st>>>(n, feat, master, wbf, norm, score);
+    k_mlp_forward<<<grid_for((n + 15) / 16, 4), 256, 0, st>>>(n, feat, master, wbf, norm, score);
     return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
 }
 
