@@ -308,38 +308,40 @@ __device__ __forceinline__ void eval_l(const LView& g, int* cnt, const unsigned*
     }
 }
 
+template <int GS>
 __device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
     const unsigned* bits = g.dbits(k);
     const int s = g.rp[w], e = g.rp[w + 1];
     const int lim = s + g.split[w];
     const int old = g.st[w];
-    const bool cached = (e - s) <= kCache * kG;
-    int xs[kCache], sv[kCache];
+    constexpr int KC = GS == 4 ? 2 * kCache : kCache;  // rows up to 64 entries stay in registers
+    const bool cached = (e - s) <= KC * GS;
+    int xs[KC], sv[KC];
     if (cached) {
 #pragma unroll
-        for (int j = 0; j < kCache; ++j) {
-            const int p = s + lig + j * kG;
+        for (int j = 0; j < KC; ++j) {
+            const int p = s + lig + j * GS;
             xs[j] = p < e ? g.col[p] : w;
         }
 #pragma unroll
-        for (int j = 0; j < kCache; ++j) sv[j] = g.st[xs[j]];
+        for (int j = 0; j < KC; ++j) sv[j] = g.st[xs[j]];
     }
     int now = 0;
     for (int base = 1;; base += 64) {
         uint64_t m = 0;
         if (cached) {
 #pragma unroll
-            for (int j = 0; j < kCache; ++j) {
+            for (int j = 0; j < KC; ++j) {
                 const unsigned c = (unsigned)(-sv[j] - base);
                 if (c < 64u) m |= 1ull << c;
             }
         } else {
-            for (int p = s + lig; p < e; p += kG) {
+            for (int p = s + lig; p < e; p += GS) {
                 const unsigned c = (unsigned)(-(int)g.st[g.col[p]] - base);
                 if (c < 64u) m |= 1ull << c;
             }
         }
-        m = gor<kG>(m);
+        m = gor<GS>(m);
         if (~m) {
             now = base + __builtin_ctzll(~m);
             break;
@@ -349,18 +351,18 @@ __device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
     bool dlow = false;
     if (cached) {
 #pragma unroll
-        for (int j = 0; j < kCache; ++j) {
-            const int p = s + lig + j * kG;
+        for (int j = 0; j < KC; ++j) {
+            const int p = s + lig + j * GS;
             if (p < e) eval_l(g, cnt, bits, k, w, p < lim, now, old, xs[j], sv[j], &c, &dlow);
         }
     } else {
-        for (int p = s + lig; p < e; p += kG) {
+        for (int p = s + lig; p < e; p += GS) {
             const int x = g.col[p];
             eval_l(g, cnt, bits, k, w, p < lim, now, old, x, g.st[x], &c, &dlow);
         }
     }
-    c = gsum<kG>(c);
-    const int d = gsum<kG>(dlow ? 1 : 0);
+    c = gsum<GS>(c);
+    const int d = gsum<GS>(dlow ? 1 : 0);
     if (lig == 0) {
         g.st[w] = (int8_t)now;
         // w is dirty, so no other group changes its counter in this phase
@@ -370,30 +372,32 @@ __device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
     }
 }
 
+template <int GS>
 __device__ void phase_b_l(const LView& g, int* cnt, int k, int w, int lig) {
     const unsigned* bits = g.dbits(k);
     const int s = g.rp[w];
     const int lim = s + g.split[w];
     const int now = g.st[w];
     int c = 0;
-    for (int p = s + lig; p < lim; p += kG) {
+    for (int p = s + lig; p < lim; p += GS) {
         const int x = g.col[p];
         if (dirty_bit(bits, x)) c += ((int)g.st[x] == now);
     }
-    c = gsum<kG>(c);
+    c = gsum<GS>(c);
     if (lig == 0) {
         const int t = lconf_add(g, w, c) + c;
         if (t == 0 && lcand(g, w)) lpush(g, cnt, cl(k), w);
     }
 }
 
+template <int GS>
 __device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
     if (lig == 0) atomicAnd(&g.cb[v >> 5], ~vbit(v));  // the candidate bit is free for the next round
     const int t = g.st[v];
     if (lconf(g, v) != 0 || t <= 0) return;  // uniform over the group
     unsigned* nbits = g.dbits(k + 1);
     const int s = g.rp[v], e = g.rp[v + 1];
-    for (int p = s + g.split[v] + lig; p < e; p += kG) {
+    for (int p = s + g.split[v] + lig; p < e; p += GS) {
         const int u = g.col[p];
         if (u == v || (int)g.st[u] != t) continue;
         if (atomicOr(&nbits[u >> 5], vbit(u)) & vbit(u)) continue;  // marked already
@@ -407,9 +411,23 @@ __device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
 
 // Rounds of graph gi (n vertices, split points set) with LDS state; the
 // caller has cleared cnt[].
+// Phase P over the m vertices of list l: 8 lanes per vertex while the list
+// fits one pass of the workgroup, else 4 (twice the vertices in flight per
+// pass for the large rounds; phase A keeps rows up to 64 entries in
+// registers either way).
+#define LDS_PHASE(P, m, l)                                                                   \
+    do {                                                                                     \
+        const int m_ = (m);                                                                  \
+        const int* l_ = (l);                                                                 \
+        if (m_ <= B / 8) {                                                                   \
+            for (int i = tid / 8; i < m_; i += B / 8) P<8>(g, cnt, k, l_[i], tid & 7);       \
+        } else {                                                                             \
+            for (int i = tid / 4; i < m_; i += B / 4) P<4>(g, cnt, k, l_[i], tid & 3);       \
+        }                                                                                    \
+    } while (0)
+
 template <int B>
 __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt, unsigned char* lds, int& kout) {
-    constexpr int kPerIt = B / kG;
     const int tid = threadIdx.x;
     LView g;
     g.n = gg.n;
@@ -439,7 +457,6 @@ __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt,
     }
     if (tid == 0) cnt[dl(2)] = 0;
     __syncthreads();
-    const int grp = tid / kG, lig = tid & (kG - 1);
     int k = 1;
     for (;; ++k) {
         if (k > 1) {
@@ -455,16 +472,16 @@ __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt,
                 cnt[dl(k + 1)] = 0;
             }
             __syncthreads();
-            for (int i = grp; i < nd; i += kPerIt) phase_a_l(g, cnt, k, g.L(dl(k))[i], lig);
+            LDS_PHASE(phase_a_l, nd, g.L(dl(k)));
             __syncthreads();
             const int nb = cnt[5];
             if (nb > 0) {
-                for (int i = grp; i < nb; i += kPerIt) phase_b_l(g, cnt, k, g.L(5)[i], lig);
+                LDS_PHASE(phase_b_l, nb, g.L(5));
                 __syncthreads();
             }
         }
         const int nc = cnt[cl(k)];
-        for (int i = grp; i < nc; i += kPerIt) phase_c_l(g, cnt, k, g.L(cl(k))[i], lig);
+        LDS_PHASE(phase_c_l, nc, g.L(cl(k)));
         __syncthreads();
     }
     kout = k;
