@@ -134,6 +134,15 @@ int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu);
 int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
 
 /*
+ * Blocks per CU of the incremental engine's three round kernels (dirty
+ * vertices, dirty-dirty counts, commits), 1..64 each, 0 = the common
+ * blocks_per_cu above (the default).  Errors: GCOLOR_EINVAL outside 0..64.
+ * Results never depend on it.
+ */
+int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_b, int32_t blocks_c);
+int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* blocks_c);
+
+/*
  * Batch tuning (process-wide, applies to later color_graph_batch calls).
  * block_threads: threads per workgroup, 256 or 1024, or 0 for the default
  * (1024 when the LDS capacity below is at least 16384 vertices, else 256).

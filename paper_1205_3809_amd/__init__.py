@@ -25,6 +25,8 @@ from ._binding import (  # noqa: F401
     get_tuning,
     get_batch_tuning,
     set_batch_tuning,
+    get_kernel_blocks,
+    set_kernel_blocks,
     profile,
     profile_read,
     raw_library,

@@ -73,6 +73,9 @@ def _load():
     lib.gcolor_set_tuning.restype = ctypes.c_int
     lib.gcolor_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.gcolor_set_batch_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gcolor_set_kernel_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gcolor_set_kernel_blocks.restype = ctypes.c_int
+    lib.gcolor_get_kernel_blocks.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.gcolor_set_batch_tuning.restype = ctypes.c_int
     lib.gcolor_get_batch_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.gcolor_get_tuning.restype = ctypes.c_int
@@ -226,6 +229,20 @@ def get_tuning():
     bpc = ctypes.c_int32()
     _lib.gcolor_get_tuning(arr, ctypes.byref(bpc))
     return list(arr), int(bpc.value)
+
+
+def set_kernel_blocks(blocks_a: int = 0, blocks_b: int = 0, blocks_c: int = 0) -> None:
+    """Blocks per CU of the three round kernels of the incremental engine
+    (0: the common blocks_per_cu of set_tuning); speed only."""
+    rc = _lib.gcolor_set_kernel_blocks(int(blocks_a), int(blocks_b), int(blocks_c))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_set_kernel_blocks")
+
+
+def get_kernel_blocks():
+    v = [ctypes.c_int32() for _ in range(3)]
+    _lib.gcolor_get_kernel_blocks(*[ctypes.byref(x) for x in v])
+    return tuple(int(x.value) for x in v)
 
 
 def set_batch_tuning(block_threads: int = 0, lds_factor: int = 8, lds_max_vertices: int = 65536) -> None:

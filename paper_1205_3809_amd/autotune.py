@@ -5,8 +5,9 @@ and the priority alone, and every candidate's colours are compared with the
 colours of the starting setting (a mismatch raises).
 
 * Single graph (color_graph): the four degree-bin limits (one lane, 4 lanes,
-  16 lanes and one wavefront per vertex; a workgroup above the last) and the
-  blocks per CU of the round grids, by coordinate descent from the current
+  16 lanes and one wavefront per vertex; a workgroup above the last), the
+  blocks per CU of the round grids and of each round kernel, by coordinate
+  descent from the current
   setting over candidate values, keeping a change only when it is faster by
   more than the noise margin.
 * Batch (color_graph_batch): threads per workgroup (256 or 1024) and the LDS
@@ -30,6 +31,7 @@ from . import _binding as B
 
 BIN_CANDIDATES = ([2, 4, 8, 16], [16, 32, 64], [64, 128, 256], [256, 384, 512, 768, 1024, 2048, 4096])
 BPC_CANDIDATES = [1, 2, 3, 4, 5, 6, 8, 12, 16]
+KERNEL_BLOCK_CANDIDATES = [0, 2, 3, 4, 6, 8, 12]  # per round kernel; 0 = blocks_per_cu
 BATCH_BLOCKS = [256, 1024]
 BATCH_FACTORS = [2, 4, 8, 16]
 BATCH_CAPS = [16384, 32768, 65536]
@@ -64,10 +66,14 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     timings of every trial."""
     out = torch.empty(row_ptr.numel() - 1, dtype=torch.int32, device=row_ptr.device)
     bins0, bpc0 = B.get_tuning()
-    cur = list(bins0) + [bpc0]
+    cur = list(bins0) + [bpc0] + list(B.get_kernel_blocks())
+
+    def setup(setting):
+        B.set_tuning(setting[:4], setting[4])
+        B.set_kernel_blocks(*setting[5:8])
 
     def run(setting):
-        B.set_tuning(setting[:4], setting[4])
+        setup(setting)
         return B.color_graph(row_ptr, col_idx, priority, out)
 
     run(cur)
@@ -77,15 +83,15 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     best_t, trials = t0, [{"setting": list(cur), "ms": round(t0, 4)}]
     for _ in range(passes):
         changed = False
-        for i in range(5):
-            for v in (BIN_CANDIDATES[i] if i < 4 else BPC_CANDIDATES):
+        for i in range(8):
+            for v in (BIN_CANDIDATES[i] if i < 4 else BPC_CANDIDATES if i == 4 else KERNEL_BLOCK_CANDIDATES):
                 trial = list(cur)
                 trial[i] = v
                 if trial == cur or any(trial[j] > trial[j + 1] for j in range(3)):
                     continue
                 t = _time_ms(lambda: run(trial), reps)
                 if not torch.equal(out, ref):
-                    B.set_tuning(cur[:4], cur[4])
+                    setup(cur)
                     raise RuntimeError("colours changed under tuning %s" % trial)
                 trials.append({"setting": trial, "ms": round(t, 4)})
                 if log:
@@ -94,9 +100,9 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
                     best_t, cur, changed = t, trial, True
         if not changed:
             break
-    B.set_tuning(cur[:4], cur[4])
-    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "ms": round(best_t, 4),
-            "start_ms": round(t0, 4), "trials": trials}
+    setup(cur)
+    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "kernel_blocks": cur[5:8],
+            "ms": round(best_t, 4), "start_ms": round(t0, 4), "trials": trials}
 
 
 def tune_batch(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.Tensor, col_idx: torch.Tensor,
@@ -165,6 +171,7 @@ def apply(table, name: str, arch_name: Optional[str] = None) -> Optional[Dict]:
         return None
     if entry["kind"] == "single":
         B.set_tuning(entry["bin_limits"], entry["blocks_per_cu"])
+        B.set_kernel_blocks(*entry.get("kernel_blocks", (0, 0, 0)))
     elif entry["kind"] == "batch":
         B.set_batch_tuning(entry["block_threads"], entry["lds_factor"], entry["lds_max_vertices"])
     else:

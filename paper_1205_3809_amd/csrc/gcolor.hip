@@ -1698,6 +1698,8 @@ std::vector<DeviceCache> g_dev;
 // Process-wide tuning: degree-bin limits and blocks per CU of the grids.
 int g_bins[4] = {8, 32, 128, 2048};
 int g_blocks_per_cu = 4;
+// blocks per CU of k_inc_a, k_inc_b, k_inc_c (0: g_blocks_per_cu)
+int g_kernel_blocks[3] = {0, 0, 0};
 
 // Optional per-kernel timing with HIP events recorded around each launch.
 enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfKinds = 5 };
@@ -1846,16 +1848,16 @@ int run_plain(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hi
 // batches between host checks; *done when the next round's dirty list is
 // empty (every vertex committed).
 template <typename S>
-int inc_rounds(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st, int* kio, int last,
+int inc_rounds(const Args& a, int64_t n, const int* grid, Launcher& L, int32_t* host, hipStream_t st, int* kio, int last,
                int* batch, bool* done) {
     int k = *kio;
     *done = false;
     while (k <= last) {
         const int nb = std::min(*batch, last - k + 1);
         for (int j = 0; j < nb; ++j, ++k) {
-            GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid, kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncB, [&] { k_inc_b<S><<<grid, kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid, kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid[0], kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncB, [&] { k_inc_b<S><<<grid[1], kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid[2], kBlock, 0, st>>>(a, k); }));
         }
         // dirty list of the next round k: empty exactly when every vertex is committed
         GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dlist(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
@@ -1882,12 +1884,12 @@ __global__ __launch_bounds__(kBlock) void k_widen(int n, const int8_t* __restric
 // a signed byte: the engine starts with 8-bit state words (half the bytes of
 // the gathers that dominate every kernel) and, if round 128 is reached,
 // widens them to 16 bits (32 when max degree + 1 exceeds 32767).
-int run_incremental(Args a, int64_t n, int vgrid, int grid, bool natural, void* wide_slot, Launcher& L,
+int run_incremental(Args a, int64_t n, int vgrid, const int* grid, bool natural, void* wide_slot, Launcher& L,
                     int32_t* host, hipStream_t st) {
     constexpr int kLast8 = 127;
     k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
-    GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid, kBlock, 0, st>>>(a, 1); }));
+    GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid[2], kBlock, 0, st>>>(a, 1); }));
     int k = 2, batch = 4;
     bool done = false;
     int rc = inc_rounds<int8_t>(a, n, grid, L, host, st, &k, kLast8, &batch, &done);
@@ -1930,10 +1932,11 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     if (!host) return GCOLOR_EHIP;
     const bool plain = (flags & GCOLOR_PLAIN) != 0;
     const bool natural = priority == nullptr;
-    int grid;
+    int grid, kgrid[3];
     {
         std::lock_guard<std::mutex> g(g_mu);
         grid = cus * g_blocks_per_cu;
+        for (int i = 0; i < 3; ++i) kgrid[i] = cus * (g_kernel_blocks[i] > 0 ? g_kernel_blocks[i] : g_blocks_per_cu);
     }
 
     k_zero_ctl<<<1, 64, 0, st>>>(ctl);
@@ -1989,7 +1992,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         }
         rc = run_plain(a, n, grid, L, host, st);
     } else {
-        rc = run_incremental(a, n, vgrid, grid, natural, base + Lw.told, L, host, st);
+        rc = run_incremental(a, n, vgrid, kgrid, natural, base + Lw.told, L, host, st);
     }
     if (rc) return rc;
 
@@ -2140,6 +2143,23 @@ int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu) {
     if (bin_limits)
         for (int i = 0; i < 4; ++i) g_bins[i] = bin_limits[i];
     if (blocks_per_cu > 0) g_blocks_per_cu = blocks_per_cu;
+    return GCOLOR_OK;
+}
+
+int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_b, int32_t blocks_c) {
+    const int32_t v[3] = {blocks_a, blocks_b, blocks_c};
+    for (int i = 0; i < 3; ++i)
+        if (v[i] < 0 || v[i] > 64) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    for (int i = 0; i < 3; ++i) g_kernel_blocks[i] = v[i];
+    return GCOLOR_OK;
+}
+
+int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* blocks_c) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (blocks_a) *blocks_a = g_kernel_blocks[0];
+    if (blocks_b) *blocks_b = g_kernel_blocks[1];
+    if (blocks_c) *blocks_c = g_kernel_blocks[2];
     return GCOLOR_OK;
 }
 

@@ -247,16 +247,20 @@ def test_result_independent_of_tuning(engine):
     ref = oracle.spec_sim(g.row_ptr, g.col_idx, key, threads=0).colors
     refn = oracle.spec_sim(g.row_ptr, g.col_idx, None, threads=0).colors
     old, bpc = gc.get_tuning()
+    kold = gc.get_kernel_blocks()
     try:
-        for bins, b in [([0, 0, 0, 0], 2), ([1, 2, 3, 4], 1), ([64, 64, 64, 64], 16), ([2, 8, 64, 256], 8),
-                        ([1000000] * 4, 3)]:
+        for bins, b, kb in [([0, 0, 0, 0], 2, (0, 0, 0)), ([1, 2, 3, 4], 1, (1, 16, 3)),
+                            ([64, 64, 64, 64], 16, (0, 0, 0)), ([2, 8, 64, 256], 8, (12, 2, 0)),
+                            ([1000000] * 4, 3, (0, 0, 0))]:
             gc.set_tuning(bins, b)
+            gc.set_kernel_blocks(*kb)
             got, _ = gpu_color(g, key, flags=engine)
-            assert np.array_equal(got, ref), (bins, b)
+            assert np.array_equal(got, ref), (bins, b, kb)
             got, _ = gpu_color(g, None, flags=engine)
-            assert np.array_equal(got, refn), (bins, b)
+            assert np.array_equal(got, refn), (bins, b, kb)
     finally:
         gc.set_tuning(old, bpc)
+        gc.set_kernel_blocks(*kold)
 
 
 def test_repeatable():
