@@ -473,6 +473,9 @@ def bench_learned(args):
     rp = torch.from_numpy(ev.row_ptr).to(dev)
     ci = torch.from_numpy(ev.col_idx).to(dev)
     out = torch.empty(ev.n, dtype=torch.int32, device=dev)
+    # launch parameters for colouring the evaluation graph (its natural order
+    # stands in for the orders compared here)
+    tuning = apply_tuning(args, "%s-eval" % args.workload, lambda: gc.autotune.tune_single(rp, ci, None, log=log))
 
     def timed(fn, reps):
         fn()
@@ -508,7 +511,8 @@ def bench_learned(args):
         "metric": "learned ordering: colours and end-to-end ms vs natural order and exact smallest-last",
         "value": round(t_learn, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": reps,
         "dtype": "int32 colouring; bf16 weights, fp32 accumulation", "data": "synthetic",
-        "config": {"workload": args.workload, "eval_n": ev.n, "eval_nnz": ev.nnz, **{k: v for k, v in p.items()}},
+        "config": {"workload": args.workload, "eval_n": ev.n, "eval_nnz": ev.nnz, **{k: v for k, v in p.items()},
+                   "tuning": tuning},
         "colours": {"natural": c_nat, "learned": c_learn, "learned_with_fallback": int(min(fb[2], fb[3])),
                     "exact_smallest_last": c_sl, "degeneracy_plus_1": degen + 1},
         "ms": {"natural": round(t_nat, 3), "learned": round(t_learn, 3), "learned_with_fallback": round(t_fb, 3),
