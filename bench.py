@@ -81,8 +81,8 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def load_traffic(workload, order, kernel, launches):
-    """HBM bytes per launch measured by rocprofv3 counters, if they were taken
+def load_traffic_file(workload, order):
+    """The stored rocprofv3 counter traffic of this workload, if it was taken
     on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
     if not os.path.exists(path):
@@ -93,7 +93,14 @@ def load_traffic(workload, order, kernel, launches):
         return None
     if d.get("kernel_source_sha256") != kernel_source_digest():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    return d
+
+
+def load_traffic(workload, order, kernel, launches):
+    """HBM bytes per launch of one kernel measured by rocprofv3 counters, if
+    they were taken on the current kernel sources; else None."""
+    d = load_traffic_file(workload, order)
+    k = (d or {}).get("kernels", {}).get(kernel)
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
@@ -108,7 +115,9 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings):
     import re
 
     def per_kernel(path, counter):
-        tot, disp, copy = {}, {}, None
+        # per round kernel: total and dispatches; every library kernel
+        # (k_zero_ctl runs once per colouring): total and colourings
+        tot, disp, copy, lib, calls = {}, {}, None, 0.0, 0
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
@@ -116,21 +125,28 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings):
             if "copyBuffer" in name and int(r["Grid_Size"]) == 131072:
                 copy = val  # the 1 GiB calibration copy
                 continue
+            if re.search(r"::k_\w+", name):
+                lib += val
+                calls += "k_zero_ctl" in name
             m = re.search(r"k_(inc_[abc]|phase[12])", name)
             if m:
                 key = m.group(1)
                 tot[key] = tot.get(key, 0.0) + val
                 disp[key] = disp.get(key, 0) + 1
-        return tot, disp, copy
+        return tot, disp, copy, lib, calls
 
-    ft, fd, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
-    wt, wd, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    ft, fd, fcopy, flib, fcalls = per_kernel(fetch_csv, "FETCH_SIZE")
+    wt, wd, wcopy, wlib, wcalls = per_kernel(write_csv, "WRITE_SIZE")
     gib_kib = 1024.0 * 1024.0
     fscale = gib_kib / fcopy if fcopy else None   # true read bytes / counted
     wscale = gib_kib / wcopy if wcopy else None
     out = {"kernel_source_sha256": kernel_source_digest(), "workload": workload, "order": order,
            "copy_calibration_kib": {"FETCH_SIZE": fcopy, "WRITE_SIZE": wcopy, "true_kib": gib_kib},
            "scale": {"FETCH_SIZE": fscale, "WRITE_SIZE": wscale}, "kernels": {}}
+    if fcalls and wcalls:
+        rd, wr = flib / fcalls * 1024.0 * fscale, wlib / wcalls * 1024.0 * wscale
+        out["per_colouring"] = {"colourings_counted": fcalls, "read_bytes": rd, "write_bytes": wr,
+                                "hbm_bytes": rd + wr}
     for k in sorted(ft):
         rd = ft[k] / fd[k] * 1024.0 * fscale
         wr = wt.get(k, 0.0) / max(wd.get(k, 1), 1) * 1024.0 * wscale
@@ -306,6 +322,13 @@ def main():
         b_plain = sum(16 * e + 32 * u for u, e in zip(U, E))
         b_min = 4 * g.nnz + 8 * g.n
         step_s = ms_per_step / 1e3
+        whole = (load_traffic_file(args.workload, args.order) or {}).get("per_colouring")
+        if whole:
+            # counter bytes of every library kernel of one colouring over the
+            # step time (the measured-traffic share of HBM peak)
+            roofline["whole_call_traffic"] = {
+                "hbm_bytes": int(whole["hbm_bytes"]), "GBps": round(whole["hbm_bytes"] / step_s / 1e9, 1),
+                "frac": round(whole["hbm_bytes"] / step_s / 1e9 / HBM_PEAK_GBS, 4)}
         roofline["effective"] = {
             "plain_method_bytes": int(b_plain), "plain_method_GBps": round(b_plain / step_s / 1e9, 1),
             "plain_method_frac": round(b_plain / step_s / 1e9 / HBM_PEAK_GBS, 4),

@@ -723,7 +723,10 @@ __device__ __forceinline__ int first_fit_long(const int* __restrict__ colp, cons
 __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __restrict__ bits, int k, int w, int p,
                                            int lim, int now, int old, int x, int sx, int* cnt, bool* dlow) {
     if (p < lim) {
-        if (is_dirty(bits, x)) *dlow = true;
+        // committed words are negative and a dirty vertex's word stays
+        // positive while this kernel rewrites it, so the bitmap is read only
+        // for uncommitted neighbours
+        if (sx > 0 && is_dirty(bits, x)) *dlow = true;
         else *cnt += (sx == now);
         return false;
     }
