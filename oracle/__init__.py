@@ -8,11 +8,13 @@ Two layers:
 
 * ``oracle.c`` (loaded through ctypes): serial greedy first-fit (Algorithm 1),
   the round-synchronous simulation of the iterative speculative colouring
-  (Algorithm 2, snapshot reads, losers revoked), and smallest-last ordering.
-  Fast enough for full-size graphs.
-* Pure-Python definitions below (``greedy_py``, ``spec_sim_py``) for small
-  inputs, written straight from the set notation, plus brute-force tools
-  (chromatic number, greedy over every ordering) used to pin the oracle.
+  (Algorithm 2, snapshot reads, losers revoked), the dataflow colouring
+  (Algorithm 3) read in rounds, and smallest-last ordering.  Fast enough for
+  full-size graphs.
+* Pure-Python definitions below (``greedy_py``, ``spec_sim_py``,
+  ``dataflow_py``) for small inputs, written straight from the set notation,
+  plus brute-force tools (chromatic number, greedy over every ordering, the
+  longest chain of preceding vertices) used to pin the oracle.
 
 Readings of the paper that the oracle fixes (the paper leaves them open):
 phase 1 reads the previous round's committed colours; losers are reset to 0;
@@ -58,6 +60,8 @@ def _load():
     lib.or_spec_sim.restype = ctypes.c_int32
     lib.or_smallest_last.argtypes = [ctypes.c_int32, i32p, i32p, i32p]
     lib.or_smallest_last.restype = ctypes.c_int32
+    lib.or_dataflow.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, i32p]
+    lib.or_dataflow.restype = ctypes.c_int32
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -118,6 +122,27 @@ def spec_sim(row_ptr, col_idx, key: Optional[np.ndarray] = None, threads: int = 
     if k < 0:
         raise RuntimeError("spec_sim: round cap %d exceeded" % max_rounds)
     return SpecResult(color[:n], int(k), fixed[:n], log[:k].copy())
+
+
+class DataflowResult(NamedTuple):
+    colors: np.ndarray    # int32[n]
+    rounds: int
+    round_of: np.ndarray  # int32[n]: round in which the vertex is coloured (1-based)
+
+
+def dataflow(row_ptr, col_idx, key: Optional[np.ndarray] = None) -> DataflowResult:
+    """Dataflow colouring (Algorithm 3) read in rounds: the colours and the
+    round of every vertex (one more than the latest round among its
+    preceding neighbours)."""
+    row_ptr, col_idx = _csr_args(row_ptr, col_idx)
+    n = row_ptr.shape[0] - 1
+    if key is not None:
+        key = np.ascontiguousarray(key, dtype=np.uint32)
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    rnd = np.zeros(max(n, 1), dtype=np.int32)
+    k = _load().or_dataflow(n, _p(row_ptr, ctypes.c_int32), _p(col_idx, ctypes.c_int32),
+                            _p(key, ctypes.c_uint32), _p(color, ctypes.c_int32), _p(rnd, ctypes.c_int32))
+    return DataflowResult(color[:n], int(k), rnd[:n])
 
 
 def smallest_last_rank(row_ptr, col_idx) -> Tuple[np.ndarray, int]:
@@ -184,6 +209,45 @@ def spec_sim_py(adj: List[List[int]], key=None, trace=None) -> Tuple[List[int], 
             trace(k, list(U), dict(tent), list(R), list(color))
         U = R
     return color, k, log
+
+
+def dataflow_py(adj: List[List[int]], key=None) -> Tuple[List[int], int, List[int]]:
+    """Algorithm 3 in rounds, from its description: each round colours, all
+    at once, every uncoloured vertex whose preceding neighbours are all
+    coloured, with the smallest colour none of them holds.  Returns
+    (colours, rounds, round of each vertex)."""
+    n = len(adj)
+    color = [0] * n
+    round_of = [0] * n
+    k = 0
+    while any(c == 0 for c in color):
+        k += 1
+        before = lambda v: [w for w in adj[v] if _order_key(key, w) < _order_key(key, v)]
+        ready = [v for v in range(n) if color[v] == 0 and all(color[w] > 0 for w in before(v))]
+        if not ready:
+            raise RuntimeError("no vertex ready")  # precedence is a strict total order: cannot happen
+        chosen = {v: first_fit({color[w] for w in before(v)}) for v in ready}
+        for v in ready:
+            color[v] = chosen[v]
+            round_of[v] = k
+    return color, k, round_of
+
+
+def longest_chain(adj: List[List[int]], key=None) -> int:
+    """Vertices on the longest path v1, v2, ... along which each vertex
+    precedes the next, by enumerating every such path (tiny graphs only)."""
+    best = 0
+
+    def walk(v: int, length: int) -> None:
+        nonlocal best
+        best = max(best, length)
+        for w in adj[v]:
+            if _order_key(key, v) < _order_key(key, w):
+                walk(w, length + 1)
+
+    for v in range(len(adj)):
+        walk(v, 1)
+    return best
 
 
 def is_proper(adj: List[List[int]], color: Sequence[int]) -> bool:

@@ -260,4 +260,49 @@ int32_t or_smallest_last(int32_t n, const int32_t* row_ptr, const int32_t* col_i
     return degeneracy;
 }
 
+/*
+ * Dataflow colouring (Algorithm 3, section "A dataflow algorithm"), read in
+ * rounds: a vertex is coloured in the round after the last of its preceding
+ * neighbours ((key, id) precedence) is coloured -- in round 1 when it has
+ * none -- with the smallest positive colour none of those neighbours holds.
+ * So
+ *   round[v] = 1 + max{round[w] : w in adj(v), w precedes v}   (1 if none),
+ *   color[v] = min{c >= 1 : c not in {color[w] : w in adj(v), w precedes v}}.
+ * Both refer only to preceding vertices, so one visit of the vertices in
+ * ascending (key, id) order fills them.  The forbidden array is stamped with
+ * the preceding neighbours' colours only (the later ones are not read).
+ * Returns the number of rounds (the largest round; 0 for n == 0).
+ */
+int32_t or_dataflow(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* key,
+                    int32_t* color, int32_t* round) {
+    const int32_t dmax = or_max_degree(n, row_ptr);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* forbidden = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax + 2));
+    for (int32_t v = 0; v < n; ++v) order[v] = v;
+    if (key) {
+        or_sort_key = key;
+        qsort(order, (size_t)n, sizeof(int32_t), or_cmp_vertex);
+    }
+    for (int32_t c = 0; c < dmax + 2; ++c) forbidden[c] = -1;
+    int32_t rounds = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t v = order[i];
+        int32_t r = 0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t w = col_idx[e];
+            if (w == v || !or_before(key, w, v)) continue;
+            forbidden[color[w]] = v;
+            if (round[w] > r) r = round[w];
+        }
+        int32_t c = 1;
+        while (forbidden[c] == v) ++c;
+        color[v] = c;
+        round[v] = r + 1;
+        if (r + 1 > rounds) rounds = r + 1;
+    }
+    free(order);
+    free(forbidden);
+    return rounds;
+}
+
 int or_num_threads(void) { return omp_get_max_threads(); }
