@@ -170,7 +170,9 @@ def main():
     ap.add_argument("--order", default="natural", choices=["natural", "perm"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timed pass")
-    ap.add_argument("--engine", default="incremental", choices=["incremental", "plain"])
+    ap.add_argument("--engine", default="incremental", choices=["incremental", "plain", "dataflow"],
+                    help="dataflow: the dataflow algorithm in rounds (a different colouring: the serial "
+                         "greedy's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--autotune", action="store_true",
@@ -210,8 +212,10 @@ def main():
     pr = None if key is None else torch.from_numpy(key.view(np.int32)).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
-    tuning = apply_tuning(args, "%s-%s" % (args.workload, args.order),
-                          lambda: gc.autotune.tune_single(rp, ci, pr, log=log))
+    flags = {"plain": gc.FLAG_PLAIN, "dataflow": gc.FLAG_DATAFLOW}.get(args.engine, 0)
+    tuning = apply_tuning(args, "%s-%s%s" % (args.workload, args.order,
+                                             "-dataflow" if args.engine == "dataflow" else ""),
+                          lambda: gc.autotune.tune_single(rp, ci, pr, log=log, flags=flags))
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
@@ -222,7 +226,6 @@ def main():
         del src, dst
 
     # one run with statistics: rounds, colours, per-round worklist and edge work
-    flags = gc.FLAG_PLAIN if args.engine == "plain" else 0
     _, st = gc.color_graph_ex(rp, ci, pr, out, flags=flags, stats=True, max_log=1 << 16)
     torch.cuda.synchronize()
     gpu_colors = out.cpu().numpy()
@@ -264,6 +267,8 @@ def main():
         torch.cuda.synchronize()
         if args.engine == "plain":
             kinds = (("phase1", gc.PROF_PHASE1), ("phase2", gc.PROF_PHASE2))
+        elif args.engine == "dataflow":
+            kinds = (("flow", gc.PROF_FLOW),)
         else:
             kinds = (("inc_a", gc.PROF_INC_A), ("inc_b", gc.PROF_INC_B), ("inc_c", gc.PROF_INC_C))
         for name, kid in kinds:
@@ -282,6 +287,13 @@ def main():
             # phase 1: neighbour id + its colour (8 B) per row entry; list entry,
             # row_ptr pair and tentative write (16 B) per worklist vertex
             algo = {"phase1": sum(8 * e + 16 * u for u, e in zip(U, E))}
+        elif args.engine == "dataflow":
+            # per vertex (once): list entry, row_ptr pair, split, colour and
+            # colour-byte writes, its append to a list (25 B); per preceding
+            # entry: neighbour id + its colour byte (5 B); per later entry:
+            # neighbour id + a read-modify-write of its counter (12 B); each
+            # undirected edge is one preceding and one later entry
+            algo = {"flow": 25 * g.n + 17 * (g.nnz // 2)}
         else:
             # state words: 1 byte in rounds 1..127, then 2 (4 when the largest
             # degree + 1 exceeds 32767)
@@ -339,7 +351,18 @@ def main():
     cpu = None
     parity = None
     greedy_colors = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.engine == "dataflow":
+        # the dataflow oracle is one ordered visit on one core
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.dataflow(g.row_ptr, g.col_idx, key)
+        dt = time.perf_counter() - t
+        parity = bool(np.array_equal(ref.colors, gpu_colors)) and ref.rounds == st.rounds
+        greedy_colors = int(ref.colors.max())
+        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload (%.1f s)" % dt}
+        log("dataflow oracle %.1fs parity=%s rounds=%d" % (dt, parity, ref.rounds))
+    elif not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
         ref = oracle.spec_sim(g.row_ptr, g.col_idx, key, threads=0)

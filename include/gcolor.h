@@ -26,8 +26,11 @@
  *   row_ptr  int32[n+1], row_ptr[0] == 0, non-decreasing, nnz = row_ptr[n] < 2^31;
  *   col_idx  int32[nnz] (may be NULL when nnz == 0), neighbour ids in [0, n); the adjacency must be
  *            symmetric (w in adj(v) iff v in adj(w)).  Without a priority array
- *            every row must be sorted ascending.  Self-loops are ignored and
- *            duplicate entries are harmless.
+ *            every row must be sorted ascending.  Self-loops are ignored.  A
+ *            neighbour may be listed more than once provided each pair is
+ *            listed equally often in both rows (as in a CSR built by
+ *            symmetrising an edge list with repeated edges); the result is
+ *            that of the graph without the repeats.
  *   priority uint32[n] or NULL.
  *   colors_out int32[n]: receives colours in [1, max degree + 1].
  * Nothing is read or written outside these extents; the library never frees
@@ -69,8 +72,17 @@ enum {
 enum {
     GCOLOR_VALIDATE = 1u << 0, /* check the CSR on the device first (costs a pass) */
     GCOLOR_STATS = 1u << 1,    /* fill *stats (rounds, colours, edge work) */
-    GCOLOR_PLAIN = 1u << 2     /* use the plain engine: every round rescans every worklist row
+    GCOLOR_PLAIN = 1u << 2,    /* use the plain engine: every round rescans every worklist row
                                   (same result as the default incremental engine) */
+    GCOLOR_DATAFLOW = 1u << 3  /* a different colouring: the dataflow algorithm (section "A
+                                  dataflow algorithm", Algorithm 3) in rounds.  A vertex is
+                                  coloured once all of its preceding neighbours are, with the
+                                  smallest colour none of them holds; the result is the serial
+                                  first-fit (Algorithm 1) visiting vertices in ascending
+                                  (priority, id) order, and the number of rounds is the number of
+                                  vertices on the longest path along which each vertex precedes
+                                  the next (n on a path in natural order).  Not combinable with
+                                  GCOLOR_PLAIN. */
 };
 
 typedef struct gcolor_stats {
@@ -87,7 +99,9 @@ typedef struct gcolor_stats {
  * number of dirty vertices (tentative colour changed), their degree sum, and
  * the row entries its dirty pass read for them (equal to the degree sum
  * except for rows longer than 512 entries, which are read without the
- * neighbours already committed). */
+ * neighbours already committed).  With GCOLOR_DATAFLOW the worklist of round
+ * k is the set of vertices coloured in it (committed == worklist), the
+ * dirty fields are 0, and edge_work over all rounds is nnz. */
 typedef struct gcolor_round {
     int64_t round;
     int64_t worklist;
@@ -162,7 +176,8 @@ int gcolor_get_batch_tuning(int32_t* block_threads, int32_t* lds_factor, int32_t
  * milliseconds and launch count of a kernel: 0 = plain phase 1 (tentative
  * colouring), 1 = plain phase 2 (conflict detection and worklist
  * compaction), 2 = incremental tentative colours of dirty vertices,
- * 3 = incremental conflict counters, 4 = incremental commit and push.
+ * 3 = incremental conflict counters, 4 = incremental commit and push,
+ * 5 = dataflow round.
  */
 int gcolor_profile(int32_t enable);
 int gcolor_profile_read(int32_t kernel, double* total_ms, int64_t* launches);

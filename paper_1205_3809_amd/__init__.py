@@ -17,11 +17,13 @@ from ._binding import (  # noqa: F401
     FLAG_VALIDATE,
     FLAG_STATS,
     FLAG_PLAIN,
+    FLAG_DATAFLOW,
     PROF_PHASE1,
     PROF_PHASE2,
     PROF_INC_A,
     PROF_INC_B,
     PROF_INC_C,
+    PROF_FLOW,
     get_tuning,
     get_batch_tuning,
     set_batch_tuning,

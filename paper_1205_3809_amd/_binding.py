@@ -19,6 +19,7 @@ _SO = os.path.join(_HERE, "libgcolor.so")
 FLAG_VALIDATE = 1
 FLAG_STATS = 2
 FLAG_PLAIN = 4
+FLAG_DATAFLOW = 8  # dataflow colouring (Algorithm 3): the serial greedy's result
 
 
 class GColorError(RuntimeError):
@@ -265,6 +266,7 @@ PROF_PHASE2 = 1   # plain engine: conflict detection + compaction
 PROF_INC_A = 2    # incremental: tentative colours of dirty vertices
 PROF_INC_B = 3    # incremental: conflict counters, candidates
 PROF_INC_C = 4    # incremental: commit + push
+PROF_FLOW = 5     # dataflow: one round
 
 
 def profile(enable: bool) -> None:

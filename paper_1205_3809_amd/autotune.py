@@ -60,10 +60,11 @@ def _time_ms(fn: Callable[[], torch.Tensor], reps: int) -> float:
 
 
 def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional[torch.Tensor] = None,
-                reps: int = 3, passes: int = 2, log: Optional[Callable[[str], None]] = None) -> Dict:
-    """Coordinate descent over (bin limits, blocks per CU) for color_graph on
-    this graph.  Leaves the best setting applied and returns it with the
-    timings of every trial."""
+                reps: int = 3, passes: int = 2, log: Optional[Callable[[str], None]] = None,
+                flags: int = 0) -> Dict:
+    """Coordinate descent over (bin limits, blocks per CU) for color_graph_ex
+    with these flags (engine choice) on this graph.  Leaves the best setting
+    applied and returns it with the timings of every trial."""
     out = torch.empty(row_ptr.numel() - 1, dtype=torch.int32, device=row_ptr.device)
     bins0, bpc0 = B.get_tuning()
     cur = list(bins0) + [bpc0] + list(B.get_kernel_blocks())
@@ -74,7 +75,7 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
 
     def run(setting):
         setup(setting)
-        return B.color_graph(row_ptr, col_idx, priority, out)
+        return B.color_graph_ex(row_ptr, col_idx, priority, out, flags=flags)
 
     run(cur)
     torch.cuda.synchronize()

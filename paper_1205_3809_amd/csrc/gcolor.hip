@@ -1403,6 +1403,197 @@ __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
     }
 }
 
+// ===========================================================================
+// Dataflow engine (section "A dataflow algorithm", Algorithm 3), in rounds.
+//
+// conf[v] counts the entries of v's preceding segment whose vertex is not
+// coloured yet.  Round k colours every vertex on its ready list (count 0)
+// with the smallest colour none of its preceding neighbours holds -- all of
+// them are final by then -- and takes one off the count of each later
+// neighbour; a count reaching 0 puts that neighbour on round k+1's list.
+// The colouring is the serial first-fit in (priority, id) order
+// (Algorithm 1), and round k holds the vertices whose longest chain of
+// preceding neighbours has k vertices.  One kernel per round.
+// Colours are gathered from a byte copy, min(colour, 255), where 255 sends
+// the reader to colors_out: a quarter of the gathered working set.
+// Lists rotate over sets 0..2: round k reads set k % 3, appends to
+// (k + 1) % 3 and clears the counts of (k + 2) % 3 (read in round k - 1,
+// filled in round k + 1).
+// ===========================================================================
+
+__host__ __device__ inline int fset(int k) { return k % 3; }
+
+__device__ __forceinline__ int flow_colour(const uint8_t* __restrict__ cb, const int* __restrict__ color, int w) {
+    const int c = cb[w];
+    return c == 255 ? color[w] : c;
+}
+
+// Colours base..base+63 held by the vertices of entries start, start +
+// STRIDE, ... < lim (all coloured); four gathers in flight per lane.
+template <int STRIDE>
+__device__ __forceinline__ uint64_t flow_window(const int* __restrict__ colp, const uint8_t* __restrict__ cb,
+                                                const int* __restrict__ color, int start, int lim, int base) {
+    uint64_t m = 0;
+    int p = start;
+    for (; p + 3 * STRIDE < lim; p += 4 * STRIDE) {
+        const int w0 = colp[p], w1 = colp[p + STRIDE], w2 = colp[p + 2 * STRIDE], w3 = colp[p + 3 * STRIDE];
+        const unsigned c0 = (unsigned)(flow_colour(cb, color, w0) - base);
+        const unsigned c1 = (unsigned)(flow_colour(cb, color, w1) - base);
+        const unsigned c2 = (unsigned)(flow_colour(cb, color, w2) - base);
+        const unsigned c3 = (unsigned)(flow_colour(cb, color, w3) - base);
+        if (c0 < 64u) m |= 1ull << c0;
+        if (c1 < 64u) m |= 1ull << c1;
+        if (c2 < 64u) m |= 1ull << c2;
+        if (c3 < 64u) m |= 1ull << c3;
+    }
+    for (; p < lim; p += STRIDE) {
+        const unsigned c = (unsigned)(flow_colour(cb, color, colp[p]) - base);
+        if (c < 64u) m |= 1ull << c;
+    }
+    return m;
+}
+
+// Later neighbours of v at entries start, start + STRIDE, ... < e: one off
+// each count; those reaching 0 go to list set `set`.  Self-loops are skipped.
+template <int STRIDE>
+__device__ __forceinline__ void flow_release(const Args& a, Stage* stg, int v, int start, int e, int set) {
+    for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
+        int x[4];
+        bool r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            x[j] = p < e ? a.colp[p] : v;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = x[j] != v && atomicSub(&a.conf[x[j]], 1) == 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) stage_append_lookup(a, stg, r[j], x[j], set);
+    }
+}
+
+__device__ __forceinline__ void flow_store(const Args& a, int v, int c) {
+    a.color[v] = c;
+    static_cast<uint8_t*>(a.st)[v] = (uint8_t)min(c, 255);
+}
+
+template <int GS>
+__device__ __forceinline__ void flow_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local,
+                                           long long* ncol, long long* work) {
+    constexpr int CV = kBlock / GS;
+    const uint8_t* cb = static_cast<const uint8_t*>(a.st);
+    const int lig = threadIdx.x & (GS - 1);
+    const int idx = local * CV + (int)threadIdx.x / GS;
+    if (idx < cnt) {
+        const int v = list[idx];
+        const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+        const int lim = s + a.split[v];
+        int c = 0;
+        for (int base = 1; c == 0; base += 64) {
+            const uint64_t m = group_or<GS>(flow_window<GS>(a.colp, cb, a.color, s + lig, lim, base));
+            if (~m) c = base + __builtin_ctzll(~m);
+        }
+        if (lig == 0) {
+            flow_store(a, v, c);
+            *ncol += 1;
+            *work += e - s;
+        }
+        flow_release<GS>(a, stg, v, lim + lig, e, fset(k + 1));
+    }
+}
+
+__device__ __forceinline__ void flow_block(const Args& a, Stage* stg, int k, int v, uint64_t* red, long long* ncol,
+                                           long long* work) {
+    const uint8_t* cb = static_cast<const uint8_t*>(a.st);
+    const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+    const int lim = s + a.split[v];
+    int c = 0;
+    for (int base = 1; c == 0; base += 64) {
+        uint64_t m = group_or<kWave>(flow_window<kBlock>(a.colp, cb, a.color, s + (int)threadIdx.x, lim, base));
+        if (__lane_id() == 0) red[threadIdx.x / kWave] = m;
+        __syncthreads();
+        m = red[0] | red[1] | red[2] | red[3];
+        __syncthreads();
+        if (~m) c = base + __builtin_ctzll(~m);
+    }
+    if (threadIdx.x == 0) {
+        flow_store(a, v, c);
+        *ncol += 1;
+        *work += e - s;
+    }
+    flow_release<kBlock>(a, stg, v, lim + (int)threadIdx.x, e, fset(k + 1));
+}
+
+// Round 1's list and the counts: conf[v] = split[v] (natural order: the
+// split is found here by binary search in the sorted row).
+__global__ __launch_bounds__(kBlock) void k_flow_seed(Args a, int natural) {
+    __shared__ Stage stg;
+    stage_init(&stg);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int i = 0; i < kLogW; ++i) a.log[i] = 0;
+    const int stride = gridDim.x * kBlock;
+    for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
+        const int v = base + (int)threadIdx.x;
+        const bool ok = v < a.n;
+        int deg = 0, sp = -1;
+        if (ok) {
+            const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+            deg = e - s;
+            if (natural) {
+                int lo = s, hi = e;
+                while (lo < hi) {
+                    const int mid = lo + ((hi - lo) >> 1);
+                    if (a.colp[mid] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                sp = lo - s;
+                a.split[v] = sp;
+            } else {
+                sp = a.split[v];
+            }
+            a.conf[v] = sp;
+            a.color[v] = 0;
+        }
+        stage_append(a, &stg, ok && sp == 0, v, deg, fset(1));
+        stage_maybe_flush(a, &stg, fset(1));
+    }
+    stage_flush(a, &stg, fset(1));
+}
+
+// Round k: colour the ready list, release later neighbours into round k+1's.
+// Log row k-1: vertices coloured and their degree sum; row k is cleared for
+// the next round.
+__global__ __launch_bounds__(kBlock) void k_flow(Args a, int k) {
+    __shared__ uint64_t red[kBlock / kWave];
+    __shared__ Stage stg;
+    const ChunkMap m = make_map(a.ctl, fset(k));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int usize = 0;
+        for (int b = 0; b < kBins; ++b) usize += m.cnt[b];
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[fset(k + 2)][b] = 0;
+        if (usize > 0) {
+            a.ctl->rounds = k;
+            if (k - 1 < kMaxLog) a.log[kLogW * (k - 1)] = usize;
+            if (k < kMaxLog)
+                for (int i = 0; i < kLogW; ++i) a.log[kLogW * k + i] = 0;
+        }
+    }
+    if ((int)blockIdx.x >= m.total) return;
+    stage_init(&stg);
+    long long ncol = 0, work = 0;
+    const int ns = fset(k + 1);
+#define F_GS(GS, L, C, LOC) flow_chunk<GS>(a, &stg, k, L, C, LOC, &ncol, &work)
+#define F_BLOCK(V) flow_block(a, &stg, k, (V), red, &ncol, &work)
+#define F_AFTER() stage_maybe_flush(a, &stg, ns)
+    GC_WALK_CHUNKS(a, m, fset(k), F_GS, F_BLOCK, F_AFTER)
+#undef F_GS
+#undef F_BLOCK
+#undef F_AFTER
+    stage_flush(a, &stg, ns);
+    block_add_log(ncol, (long long*)&a.ctl->committed);
+    if (k - 1 < kMaxLog) block_add_log(work, &a.log[kLogW * (k - 1) + 1]);
+}
+
 // Largest row length (the colour bound Delta + 1 picks the state width).
 __global__ __launch_bounds__(kBlock) void k_maxdeg(int n, const int* __restrict__ row_ptr, Ctl* ctl) {
     int mx = 0;
@@ -1705,7 +1896,7 @@ int g_blocks_per_cu = 4;
 int g_kernel_blocks[3] = {0, 0, 0};
 
 // Optional per-kernel timing with HIP events recorded around each launch.
-enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfKinds = 5 };
+enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfFlow = 5, kProfKinds = 6 };
 bool g_prof = false;
 double g_prof_ms[kProfKinds] = {};
 int64_t g_prof_launches[kProfKinds] = {};
@@ -1876,6 +2067,29 @@ int inc_rounds(const Args& a, int64_t n, const int* grid, Launcher& L, int32_t* 
     return GCOLOR_OK;
 }
 
+// Dataflow rounds in batches between host checks (the batch grows to 256
+// rounds: a natural-order graph can need tens of thousands).
+int run_dataflow(const Args& a, int64_t n, int vgrid, int grid, bool natural, Launcher& L, int32_t* host,
+                 hipStream_t st) {
+    k_flow_seed<<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    GC_CHECK(hipGetLastError());
+    int k = 1, batch = 4;
+    for (;;) {
+        for (int j = 0; j < batch; ++j, ++k)
+            GC_CHECK(L(kProfFlow, [&] { k_flow<<<grid, kBlock, 0, st>>>(a, k); }));
+        // round k's list (the next to run): empty once nothing is left to release
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[fset(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipStreamSynchronize(st));
+        if (sum_counts(host) == 0) break;
+        if (k > n + 64) return GCOLOR_EROUNDS;
+        batch = std::min(batch * 2, 256);
+    }
+    unsigned long long coloured = 0;
+    GC_CHECK(hipMemcpyAsync(&coloured, &a.ctl->committed, sizeof(coloured), hipMemcpyDeviceToHost, st));
+    GC_CHECK(hipStreamSynchronize(st));
+    return coloured == (unsigned long long)n ? GCOLOR_OK : GCOLOR_EINTERNAL;
+}
+
 // Widen the state words into another slot (int8 -> int16 / int32).
 template <typename D>
 __global__ __launch_bounds__(kBlock) void k_widen(int n, const int8_t* __restrict__ src, D* __restrict__ dst) {
@@ -1934,6 +2148,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     int32_t* host = pinned_buffer();
     if (!host) return GCOLOR_EHIP;
     const bool plain = (flags & GCOLOR_PLAIN) != 0;
+    const bool flow = (flags & GCOLOR_DATAFLOW) != 0;
     const bool natural = priority == nullptr;
     int grid, kgrid[3];
     {
@@ -1994,6 +2209,8 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
             GC_CHECK(hipGetLastError());
         }
         rc = run_plain(a, n, grid, L, host, st);
+    } else if (flow) {
+        rc = run_dataflow(a, n, vgrid, grid, natural, L, host, st);
     } else {
         rc = run_incremental(a, n, vgrid, kgrid, natural, base + Lw.told, L, host, st);
     }
@@ -2030,6 +2247,13 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
                 U[r] = hl[kLogW * r];
                 E[r] = hl[kLogW * r + 1];
                 C[r] = U[r] - (r + 1 < nl ? hl[kLogW * (r + 1)] : 0);
+            }
+        } else if (flow) {
+            // the round's list is coloured whole
+            for (int r = 0; r < nl; ++r) {
+                U[r] = hl[kLogW * r];
+                E[r] = hl[kLogW * r + 1];
+                C[r] = U[r];
             }
         } else {
             long long u = n, e = nnz;
@@ -2090,7 +2314,8 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, co
                    int32_t* colors_out, void* workspace, size_t ws_bytes, uint32_t flags,
                    gcolor_stats_t* stats, gcolor_round_t* round_log, int32_t max_log, gcolor_stream_t stream) {
     if (n < 0) return GCOLOR_EINVAL;
-    if (flags & ~(uint32_t)(GCOLOR_VALIDATE | GCOLOR_STATS | GCOLOR_PLAIN)) return GCOLOR_EINVAL;
+    if (flags & ~(uint32_t)(GCOLOR_VALIDATE | GCOLOR_STATS | GCOLOR_PLAIN | GCOLOR_DATAFLOW)) return GCOLOR_EINVAL;
+    if ((flags & GCOLOR_PLAIN) && (flags & GCOLOR_DATAFLOW)) return GCOLOR_EINVAL;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (n == 0) return GCOLOR_OK;
     if (!row_ptr || !colors_out) return GCOLOR_EINVAL;
