@@ -542,10 +542,21 @@ def bench_learned(args):
     def learned_fb():
         return L.color_learned(model, rp, ci, fallback=True)
 
+    def ordering_only():
+        return L.order_learned(model, rp, ci)[0]
+
+    def learned_flow():
+        keys, _ = L.order_learned(model, rp, ci)
+        return gc.color_graph_ex(rp, ci, keys, out, flags=gc.FLAG_DATAFLOW, stats=True)[1]
+
     reps = max(1, args.steps)
     t_nat, c_nat = timed(natural, reps)
+    t_order, _ = timed(ordering_only, reps)
     t_learn, c_learn = timed(learned, reps)
     t_fb, fb = timed(learned_fb, reps)
+    # the dataflow engine with the same learned keys: the serial greedy's
+    # colouring in the learned order
+    t_lflow, st_lflow = timed(learned_flow, reps)
     # exact smallest-last: the library's host routine (the order is a
     # sequential peel), keys to the device, same colouring
     w = time.perf_counter()
@@ -553,6 +564,8 @@ def bench_learned(args):
     t_sl_order = (time.perf_counter() - w) * 1000.0
     slk = torch.from_numpy(rank.astype(np.int32)).to(dev)
     t_sl_col, c_sl = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, stats=True)[1].num_colors, reps)
+    t_sl_flow, st_sl_flow = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, flags=gc.FLAG_DATAFLOW,
+                                                            stats=True)[1], reps)
     res = {
         "metric": "learned ordering: colours and end-to-end ms vs natural order and exact smallest-last",
         "value": round(t_learn, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": reps,
@@ -560,10 +573,16 @@ def bench_learned(args):
         "config": {"workload": args.workload, "eval_n": ev.n, "eval_nnz": ev.nnz, **{k: v for k, v in p.items()},
                    "tuning": tuning},
         "colours": {"natural": c_nat, "learned": c_learn, "learned_with_fallback": int(min(fb[2], fb[3])),
-                    "exact_smallest_last": c_sl, "degeneracy_plus_1": degen + 1},
+                    "exact_smallest_last": c_sl, "degeneracy_plus_1": degen + 1,
+                    "learned_dataflow": int(st_lflow.num_colors),
+                    "exact_smallest_last_dataflow": int(st_sl_flow.num_colors)},
         "ms": {"natural": round(t_nat, 3), "learned": round(t_learn, 3), "learned_with_fallback": round(t_fb, 3),
+               "learned_ordering_only": round(t_order, 3),
+               "learned_dataflow": round(t_lflow, 3),
                "exact_smallest_last_order_host": round(t_sl_order, 1),
-               "exact_smallest_last_total": round(t_sl_order + t_sl_col, 1)},
+               "exact_smallest_last_total": round(t_sl_order + t_sl_col, 1),
+               "exact_smallest_last_dataflow_colouring": round(t_sl_flow, 3)},
+        "dataflow_rounds": {"learned": int(st_lflow.rounds), "exact_smallest_last": int(st_sl_flow.rounds)},
         "training": {"seconds": round(train_s, 2), "vertices": rep.vertices, "final_minibatch_loss":
                      round(rep.losses[-1], 6)},
     }
