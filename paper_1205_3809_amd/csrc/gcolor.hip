@@ -1659,38 +1659,39 @@ __device__ __forceinline__ bool precedes(const uint32_t* __restrict__ key, int w
     return kw < kv || (kw == kv && w < v);
 }
 
-// Priority order, step 2: copy each row with the preceding neighbours first.
+// Priority order, step 2: copy each row with the preceding neighbours first,
+// in one pass: preceding entries fill the row from its start upwards, later
+// ones from its end downwards (the order inside each segment is irrelevant
+// to every engine), so each neighbour's key is gathered once.
 template <int GS>
 __device__ __forceinline__ void reorder_group(const int* __restrict__ col, int* __restrict__ out,
                                               int* __restrict__ split, const uint32_t* __restrict__ key,
                                               int v, int s, int e, int lig, int lane) {
     const uint32_t kv = key[v];
-    int nlo = 0;
-    for (int p0 = s; p0 < e; p0 += GS) {
-        const int p = p0 + lig;
-        const bool lo = (p < e) && precedes(key, col[p], kv, v);
-        nlo += __popcll(group_bits<GS>(__ballot(lo), lane));
-    }
-    int plo = s, phi = s + nlo;
+    int plo = s, phi = e;
     const uint64_t below = (lig == 0) ? 0ull : ((1ull << lig) - 1ull);
-    for (int p0 = s; p0 < e; p0 += GS) {
-        const int p = p0 + lig;
-        int w = 0;
-        bool lo = false;
-        if (p < e) {
-            w = col[p];
-            lo = precedes(key, w, kv, v);
+    for (int p0 = s; p0 < e; p0 += 4 * GS) {
+        int w[4];
+        bool in[4], lo[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * GS + lig;
+            in[j] = p < e;
+            w[j] = in[j] ? col[p] : v;
         }
-        const uint64_t blo = group_bits<GS>(__ballot(p < e && lo), lane);
-        const uint64_t bhi = group_bits<GS>(__ballot(p < e && !lo), lane);
-        if (p < e) {
-            if (lo) out[plo + __popcll(blo & below)] = w;
-            else out[phi + __popcll(bhi & below)] = w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lo[j] = in[j] && precedes(key, w[j], kv, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t blo = group_bits<GS>(__ballot(lo[j]), lane);
+            const uint64_t bhi = group_bits<GS>(__ballot(in[j] && !lo[j]), lane);
+            if (lo[j]) out[plo + __popcll(blo & below)] = w[j];
+            else if (in[j]) out[phi - 1 - __popcll(bhi & below)] = w[j];
+            plo += __popcll(blo);
+            phi -= __popcll(bhi);
         }
-        plo += __popcll(blo);
-        phi += __popcll(bhi);
     }
-    if (lig == 0) split[v] = nlo;
+    if (lig == 0) split[v] = plo - s;
 }
 
 template <int GS>
@@ -1706,8 +1707,9 @@ __device__ __forceinline__ void reorder_chunk(const Args& a, const int* col, int
     }
 }
 
-// One workgroup per hub row: two passes of 256-entry tiles with a block-wide
-// exclusive count of the preceding neighbours.
+// One workgroup per hub row: one pass of 256-entry tiles with block-wide
+// offsets, preceding entries upwards from the start, later ones downwards
+// from the end.
 __device__ void reorder_hub(const Args& a, const int* __restrict__ col, int* __restrict__ out,
                             int* __restrict__ split, const uint32_t* __restrict__ key, int v, int* sh) {
     const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
@@ -1715,13 +1717,7 @@ __device__ void reorder_hub(const Args& a, const int* __restrict__ col, int* __r
     const int wid = threadIdx.x / kWave;
     const uint32_t kv = key[v];
     const uint64_t below = __lanemask_lt();
-    int nlo = 0;
-    for (int p0 = s; p0 < e; p0 += kBlock) {
-        const int p = p0 + (int)threadIdx.x;
-        const bool lo = (p < e) && precedes(key, col[p], kv, v);
-        nlo += __syncthreads_count(lo);
-    }
-    int plo = s, phi = s + nlo;
+    int plo = s, phi = e;
     for (int p0 = s; p0 < e; p0 += kBlock) {
         const int p = p0 + (int)threadIdx.x;
         int w = 0;
@@ -1749,12 +1745,12 @@ __device__ void reorder_hub(const Args& a, const int* __restrict__ col, int* __r
         __syncthreads();
         if (p < e) {
             if (lo) out[plo + olo + __popcll(blo & below)] = w;
-            else out[phi + ohi + __popcll(bhi & below)] = w;
+            else out[phi - 1 - ohi - __popcll(bhi & below)] = w;
         }
         plo += tlo;
-        phi += thi;
+        phi -= thi;
     }
-    if (threadIdx.x == 0) split[v] = nlo;
+    if (threadIdx.x == 0) split[v] = plo - s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_reorder(Args a, const int* __restrict__ col, int* __restrict__ out,
