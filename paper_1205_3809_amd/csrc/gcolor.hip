@@ -1453,10 +1453,19 @@ __device__ __forceinline__ uint64_t flow_window(const int* __restrict__ colp, co
     return m;
 }
 
-// Later neighbours of v at entries start, start + STRIDE, ... < e: one off
-// each count; those reaching 0 go to list set `set`.  Self-loops are skipped.
+__device__ __forceinline__ void flow_store(const Args& a, int v, int c) {
+    a.color[v] = c;
+    static_cast<uint8_t*>(a.st)[v] = (uint8_t)min(c, 255);
+}
+
+// One pass over the whole row of v, entries start, start + STRIDE, ... < e:
+// preceding entries (below lim) add their colours in 1..64 to the mask,
+// later ones are released at once -- the released vertices read v's colour
+// only in the next round, so nothing here waits for the first-fit.
 template <int STRIDE>
-__device__ __forceinline__ void flow_release(const Args& a, Stage* stg, int v, int start, int e, int set) {
+__device__ __forceinline__ uint64_t flow_row(const Args& a, Stage* stg, const uint8_t* __restrict__ cb, int v,
+                                             int start, int lim, int e, int set) {
+    uint64_t m = 0;
     for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
         int x[4];
         bool r[4];
@@ -1466,15 +1475,20 @@ __device__ __forceinline__ void flow_release(const Args& a, Stage* stg, int v, i
             x[j] = p < e ? a.colp[p] : v;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = x[j] != v && atomicSub(&a.conf[x[j]], 1) == 1;
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j * STRIDE;
+            r[j] = false;
+            if (p < lim) {
+                const unsigned c = (unsigned)(flow_colour(cb, a.color, x[j]) - 1);
+                if (c < 64u) m |= 1ull << c;
+            } else if (x[j] != v) {
+                r[j] = atomicSub(&a.conf[x[j]], 1) == 1;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) stage_append_lookup(a, stg, r[j], x[j], set);
     }
-}
-
-__device__ __forceinline__ void flow_store(const Args& a, int v, int c) {
-    a.color[v] = c;
-    static_cast<uint8_t*>(a.st)[v] = (uint8_t)min(c, 255);
+    return m;
 }
 
 template <int GS>
@@ -1488,9 +1502,10 @@ __device__ __forceinline__ void flow_chunk(const Args& a, Stage* stg, int k, con
         const int v = list[idx];
         const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
         const int lim = s + a.split[v];
-        int c = 0;
-        for (int base = 1; c == 0; base += 64) {
-            const uint64_t m = group_or<GS>(flow_window<GS>(a.colp, cb, a.color, s + lig, lim, base));
+        uint64_t m = group_or<GS>(flow_row<GS>(a, stg, cb, v, s + lig, lim, e, fset(k + 1)));
+        int c = ~m ? 1 + __builtin_ctzll(~m) : 0;
+        for (int base = 65; c == 0; base += 64) {  // colours 1..64 all taken
+            m = group_or<GS>(flow_window<GS>(a.colp, cb, a.color, s + lig, lim, base));
             if (~m) c = base + __builtin_ctzll(~m);
         }
         if (lig == 0) {
@@ -1498,7 +1513,6 @@ __device__ __forceinline__ void flow_chunk(const Args& a, Stage* stg, int k, con
             *ncol += 1;
             *work += e - s;
         }
-        flow_release<GS>(a, stg, v, lim + lig, e, fset(k + 1));
     }
 }
 
@@ -1507,9 +1521,11 @@ __device__ __forceinline__ void flow_block(const Args& a, Stage* stg, int k, int
     const uint8_t* cb = static_cast<const uint8_t*>(a.st);
     const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
     const int lim = s + a.split[v];
+    uint64_t m = flow_row<kBlock>(a, stg, cb, v, s + (int)threadIdx.x, lim, e, fset(k + 1));
     int c = 0;
     for (int base = 1; c == 0; base += 64) {
-        uint64_t m = group_or<kWave>(flow_window<kBlock>(a.colp, cb, a.color, s + (int)threadIdx.x, lim, base));
+        if (base > 1) m = flow_window<kBlock>(a.colp, cb, a.color, s + (int)threadIdx.x, lim, base);
+        m = group_or<kWave>(m);
         if (__lane_id() == 0) red[threadIdx.x / kWave] = m;
         __syncthreads();
         m = red[0] | red[1] | red[2] | red[3];
@@ -1521,7 +1537,6 @@ __device__ __forceinline__ void flow_block(const Args& a, Stage* stg, int k, int
         *ncol += 1;
         *work += e - s;
     }
-    flow_release<kBlock>(a, stg, v, lim + (int)threadIdx.x, e, fset(k + 1));
 }
 
 // Round 1's list and the counts: conf[v] = split[v] (natural order: the
