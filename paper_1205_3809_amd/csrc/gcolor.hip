@@ -110,7 +110,6 @@ struct Args {
     int* __restrict__ tent;        // (plain) tentative colour
     void* st;                      // (incremental) state words, int8_t, int16_t or int32_t
     int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
-    int* __restrict__ stamp;       // (incremental) round of last dirty mark
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
     int* __restrict__ lists;       // [kSets][kBins][n]
     unsigned* __restrict__ dbits;  // (incremental) 3 dirty bitmaps of nwords words
@@ -586,7 +585,6 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
             }
             st[v] = 1;
             a.conf[v] = sp;
-            a.stamp[v] = 0;
             a.cflag[v] = 0;
         }
         // heavy rows: an id each (wave-aggregated) and the whole row as the
@@ -1279,10 +1277,11 @@ __global__ __launch_bounds__(kBlock) void k_inc_b(Args a, int k) {
 __device__ __forceinline__ bool inc_c_eval(const Args& a, unsigned* __restrict__ nbits, int k, int v, int u, int su,
                                            int t) {
     if (u == v || su != t) return false;
-    if (a.stamp[u] == k + 1) return false;
-    if (atomicExch(&a.stamp[u], k + 1) == k + 1) return false;
-    atomicOr(&nbits[u >> 5], 1u << (u & 31));
-    return true;
+    // round k+1's bitmap is clear when this kernel starts, so the atomic that
+    // sets the bit is the first mark (a plain read first skips most repeats)
+    const unsigned bit = 1u << (u & 31);
+    if (nbits[u >> 5] & bit) return false;
+    return !(atomicOr(&nbits[u >> 5], bit) & bit);
 }
 
 template <int STRIDE, typename S>
@@ -1863,7 +1862,7 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, stamp, cflag, split, lists, dbits, colp, hid, hrow, hF, act, total;
+    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, colp, hid, hrow, hF, act, total;
 };
 
 Layout layout(int32_t n, int64_t nnz) {
@@ -1875,7 +1874,6 @@ Layout layout(int32_t n, int64_t nnz) {
     L.tent = off;  off += align_up(vn);
     L.told = off;  off += align_up(vn);
     L.conf = off;  off += align_up(vn);
-    L.stamp = off; off += align_up(vn);
     L.cflag = off; off += align_up(vn);
     L.split = off; off += align_up(vn);
     L.lists = off; off += align_up(vn * kSets * kBins);
@@ -2185,7 +2183,6 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     // the incremental engine's state words share the plain engine's slots
     a.st = base + Lw.tent;
     a.conf = reinterpret_cast<int*>(base + Lw.conf);
-    a.stamp = reinterpret_cast<int*>(base + Lw.stamp);
     a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
     a.lists = reinterpret_cast<int*>(base + Lw.lists);
     a.dbits = reinterpret_cast<unsigned*>(base + Lw.dbits);
