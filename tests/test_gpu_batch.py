@@ -96,6 +96,18 @@ def test_batch_single_and_large_graph():
     check_batch([graphgen.rmat(15, 8, (0.55, 0.1, 0.1), 3), graphgen.empty(3)])
 
 
+@pytest.mark.parametrize("count", [8192, 8193])
+def test_batch_at_and_past_the_sort_limit(count):
+    """Up to 8192 graphs are processed largest first (sorted in LDS), more
+    in index order; either way every graph is coloured as alone."""
+    specs = graphgen.batch_specs(count, 40 + count, 3.0, 7.0)
+    graphs = [graphgen.batch_graph(s) for s in specs]
+    graphs[count // 2] = graphgen.grid((40, 40), True)  # one large graph in the middle
+    graphs[-1] = graphgen.empty(0)
+    print("batch of %d graphs" % count, flush=True)
+    check_batch(graphs)
+
+
 def test_batch_graph_capture_replays():
     check_batch(mixed_graphs(7, count=24), capture=True)
 
