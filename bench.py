@@ -186,8 +186,8 @@ def main():
     if WORKLOADS[args.workload][0] == "learned" and args.gpus == 1:
         return bench_learned(args)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
-              "sharding of the method is described in the design notes but not built." % args.gpus,
+        print("bench.py: the colouring runs on one GPU (got --gpus %d); sharding the method across "
+              "GPUs is not built." % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -64,7 +64,7 @@ enum {
     GCOLOR_EWORKSPACE = -3, /* caller workspace smaller than gcolor_workspace_bytes */
     GCOLOR_EHIP = -4,       /* a HIP runtime call failed */
     GCOLOR_EROUNDS = -5,    /* round cap exceeded (never happens for valid input) */
-    GCOLOR_ENOTSUP = -6,    /* sizes beyond what this build supports */
+    GCOLOR_ENOTSUP = -6,    /* sizes beyond what the library supports */
     GCOLOR_EINTERNAL = -7   /* an internal consistency check failed (a bug; report it) */
 };
 
