@@ -309,10 +309,9 @@ __device__ __forceinline__ void eval_l(const LView& g, int* cnt, const unsigned*
 }
 
 template <int GS>
-__device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
+__device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int s, int e, int sp, int lig) {
     const unsigned* bits = g.dbits(k);
-    const int s = g.rp[w], e = g.rp[w + 1];
-    const int lim = s + g.split[w];
+    const int lim = s + sp;
     const int old = g.st[w];
     constexpr int KC = GS == 4 ? 2 * kCache : kCache;  // rows up to 64 entries stay in registers
     const bool cached = (e - s) <= KC * GS;
@@ -373,10 +372,9 @@ __device__ void phase_a_l(const LView& g, int* cnt, int k, int w, int lig) {
 }
 
 template <int GS>
-__device__ void phase_b_l(const LView& g, int* cnt, int k, int w, int lig) {
+__device__ void phase_b_l(const LView& g, int* cnt, int k, int w, int s, int e, int sp, int lig) {
     const unsigned* bits = g.dbits(k);
-    const int s = g.rp[w];
-    const int lim = s + g.split[w];
+    const int lim = s + sp;
     const int now = g.st[w];
     int c = 0;
     for (int p = s + lig; p < lim; p += GS) {
@@ -391,13 +389,12 @@ __device__ void phase_b_l(const LView& g, int* cnt, int k, int w, int lig) {
 }
 
 template <int GS>
-__device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
+__device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int s, int e, int sp, int lig) {
     if (lig == 0) atomicAnd(&g.cb[v >> 5], ~vbit(v));  // the candidate bit is free for the next round
     const int t = g.st[v];
     if (lconf(g, v) != 0 || t <= 0) return;  // uniform over the group
     unsigned* nbits = g.dbits(k + 1);
-    const int s = g.rp[v], e = g.rp[v + 1];
-    for (int p = s + g.split[v] + lig; p < e; p += GS) {
+    for (int p = s + sp + lig; p < e; p += GS) {
         const int u = g.col[p];
         if (u == v || (int)g.st[u] != t) continue;
         if (atomicOr(&nbits[u >> 5], vbit(u)) & vbit(u)) continue;  // marked already
@@ -409,21 +406,56 @@ __device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int lig) {
     }
 }
 
+// Walk list l[0..m) with groups of GS lanes (vertex i to group tid / GS,
+// then i + B / GS, ...), calling body(w, row start, row end, split).  Each
+// group loads the row offsets and split of its next vertex, and the list
+// entry of the one after, before it processes the current one, so that a
+// vertex waits for one global access (its row) instead of three in a chain.
+template <int B, int GS, typename F>
+__device__ __forceinline__ void lds_walk(const LView& g, const int* l, int m, int tid, F&& body) {
+    constexpr int STEP = B / GS;
+    int i = tid / GS;
+    if (i >= m) return;
+    int w = l[i];
+    int s = g.rp[w], e = g.rp[w + 1], sp = g.split[w];
+    int wn = i + STEP < m ? l[i + STEP] : 0;
+    for (;;) {
+        const int in = i + STEP;
+        int sn = 0, en = 0, spn = 0, wnn = 0;
+        if (in < m) {
+            sn = g.rp[wn];
+            en = g.rp[wn + 1];
+            spn = g.split[wn];
+        }
+        if (in + STEP < m) wnn = l[in + STEP];
+        body(w, s, e, sp);
+        if (in >= m) break;
+        i = in;
+        w = wn;
+        s = sn;
+        e = en;
+        sp = spn;
+        wn = wnn;
+    }
+}
+
 // Rounds of graph gi (n vertices, split points set) with LDS state; the
 // caller has cleared cnt[].
 // Phase P over the m vertices of list l: 8 lanes per vertex while the list
 // fits one pass of the workgroup, else 4 (twice the vertices in flight per
 // pass for the large rounds; phase A keeps rows up to 64 entries in
 // registers either way).
-#define LDS_PHASE(P, m, l)                                                                   \
-    do {                                                                                     \
-        const int m_ = (m);                                                                  \
-        const int* l_ = (l);                                                                 \
-        if (m_ <= B / 8) {                                                                   \
-            for (int i = tid / 8; i < m_; i += B / 8) P<8>(g, cnt, k, l_[i], tid & 7);       \
-        } else {                                                                             \
-            for (int i = tid / 4; i < m_; i += B / 4) P<4>(g, cnt, k, l_[i], tid & 3);       \
-        }                                                                                    \
+#define LDS_PHASE(P, m, l)                                                                            \
+    do {                                                                                              \
+        const int m_ = (m);                                                                           \
+        const int* l_ = (l);                                                                          \
+        if (m_ <= B / 8) {                                                                            \
+            lds_walk<B, 8>(g, l_, m_, tid,                                                            \
+                           [&](int w_, int s_, int e_, int p_) { P<8>(g, cnt, k, w_, s_, e_, p_, tid & 7); }); \
+        } else {                                                                                      \
+            lds_walk<B, 4>(g, l_, m_, tid,                                                            \
+                           [&](int w_, int s_, int e_, int p_) { P<4>(g, cnt, k, w_, s_, e_, p_, tid & 3); }); \
+        }                                                                                             \
     } while (0)
 
 template <int B>
