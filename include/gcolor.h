@@ -88,7 +88,8 @@ enum {
 typedef struct gcolor_stats {
     int32_t rounds;     /* number of rounds (a round = phase 1 + phase 2) */
     int32_t num_colors; /* largest colour assigned */
-    int64_t edge_work;  /* sum over rounds of the degrees of the worklist */
+    int64_t edge_work;  /* sum over rounds of the degrees of the worklist (the first 65536
+                           rounds: the device keeps per-round records for those) */
     int32_t status;     /* 0, or the code the call returned */
     int32_t reserved;
 } gcolor_stats_t;
@@ -127,8 +128,8 @@ int color_graph(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
  * As color_graph, with a caller-provided device workspace of ws_bytes bytes
  * (>= gcolor_workspace_bytes(n, nnz); NULL selects the library's own), flags
  * (GCOLOR_*), optional host pointers: stats (filled when GCOLOR_STATS is set)
- * and round_log (capacity max_log records; the first min(rounds, max_log)
- * rounds are written).
+ * and round_log (capacity max_log records; the first min(rounds, max_log,
+ * 65536) rounds are written).
  */
 int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint32_t* priority, int32_t* colors_out, void* workspace,
