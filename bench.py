@@ -566,6 +566,14 @@ def bench_learned(args):
     t_sl_col, c_sl = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, stats=True)[1].num_colors, reps)
     t_sl_flow, st_sl_flow = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, flags=gc.FLAG_DATAFLOW,
                                                             stats=True)[1], reps)
+    # reference order: largest degree first (ties by id), keys built here on
+    # the host; the colouring is timed alone
+    deg = np.diff(ev.row_ptr.astype(np.int64))
+    lf_order = np.lexsort((np.arange(ev.n), -deg))
+    lf_key = np.empty(ev.n, dtype=np.int32)
+    lf_key[lf_order] = np.arange(ev.n, dtype=np.int32)
+    lfk = torch.from_numpy(lf_key).to(dev)
+    t_lf_col, c_lf = timed(lambda: gc.color_graph_ex(rp, ci, lfk, out, stats=True)[1].num_colors, reps)
     res = {
         "metric": "learned ordering: colours and end-to-end ms vs natural order and exact smallest-last",
         "value": round(t_learn, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": reps,
@@ -574,10 +582,12 @@ def bench_learned(args):
                    "tuning": tuning},
         "colours": {"natural": c_nat, "learned": c_learn, "learned_with_fallback": int(min(fb[2], fb[3])),
                     "exact_smallest_last": c_sl, "degeneracy_plus_1": degen + 1,
+                    "largest_degree_first": c_lf,
                     "learned_dataflow": int(st_lflow.num_colors),
                     "exact_smallest_last_dataflow": int(st_sl_flow.num_colors)},
         "ms": {"natural": round(t_nat, 3), "learned": round(t_learn, 3), "learned_with_fallback": round(t_fb, 3),
                "learned_ordering_only": round(t_order, 3),
+               "largest_degree_first_colouring": round(t_lf_col, 3),
                "learned_dataflow": round(t_lflow, 3),
                "exact_smallest_last_order_host": round(t_sl_order, 1),
                "exact_smallest_last_total": round(t_sl_order + t_sl_col, 1),
