@@ -106,7 +106,7 @@ def load_traffic(workload, order, kernel, launches):
     return k.get("hbm_bytes_per_launch")
 
 
-def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings):
+def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings, out_path=None):
     """Write profiles/traffic_<workload>_<order>.json from two rocprofv3 --pmc
     runs of this script (FETCH_SIZE, then WRITE_SIZE, both with
     --copy-calibration).  Each counter is scaled by what it reads for the
@@ -152,9 +152,10 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings):
         wr = wt.get(k, 0.0) / max(wd.get(k, 1), 1) * 1024.0 * wscale
         out["kernels"][k] = {"launches_counted": fd[k], "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
                              "hbm_bytes_per_launch": rd + wr}
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
+    path = out_path or os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
     json.dump(out, open(path, "w"), indent=1, sort_keys=True)
     print(path)
+    return out
 
 
 def main():
