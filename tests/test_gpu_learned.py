@@ -46,6 +46,20 @@ def test_features_match_oracle():
         assert np.allclose(got, ref, rtol=2e-6, atol=1e-6)
 
 
+def test_features_at_evaluation_scale():
+    """All features of every vertex of the scale-22 evaluation graph (hubs
+    above 160,000 neighbours): integer features exact, the others within
+    2e-6 relative."""
+    from paper_1205_3809_amd import learned as L
+    g = graphgen.rmat(22, 16, TRAIN_ABCD, 1000)
+    print("features rmat22: n=%d nnz=%d" % (g.n, g.nnz), flush=True)
+    got = L.features(dev(g.row_ptr), dev(g.col_idx), 123).cpu().numpy().astype(np.float64)
+    ref = OL.features(g.row_ptr, g.col_idx, 123)
+    for f in (0, 2, 4, 7):
+        assert np.array_equal(got[:, f], ref[:, f]), f
+    assert np.allclose(got, ref, rtol=2e-6, atol=1e-6)
+
+
 def _model_with_norm(g_feats_ref, seed=0):
     from paper_1205_3809_amd import learned as L
     m = L.MLP(seed=seed)

@@ -331,6 +331,27 @@ def test_rmat_scale20_natural(abc):
     check(rmat(20, 8, abc, 11), label="rmat20")
 
 
+@pytest.mark.parametrize("order", ["natural", "ties8"])
+def test_skewed_scale22_in_its_bench_configuration(order):
+    """The learned-ordering evaluation graph (R-MAT scale 22, edge factor 16,
+    (0.57, 0.19, 0.19, 0.05), seed 1000) coloured with the launch parameters
+    the bench applies to it (tuning table entry learned22-eval), in natural
+    order and with 8-bit keys (many ties, like quantised learned scores)."""
+    import paper_1205_3809_amd as gc
+    from paper_1205_3809_amd import autotune
+    g = rmat(22, 16, (0.57, 0.19, 0.19), 1000)
+    key = None if order == "natural" else graphgen.random_keys(g.n, 77, bits=8)
+    old, bpc = gc.get_tuning()
+    kold = gc.get_kernel_blocks()
+    try:
+        entry = autotune.apply(autotune.TABLE, "learned22-eval", "gfx950")
+        assert entry is not None
+        check(g, key, label="rmat22-skewed-" + order, engines=(("incremental", 0),))
+    finally:
+        gc.set_tuning(old, bpc)
+        gc.set_kernel_blocks(*kold)
+
+
 @pytest.mark.parametrize("order", ["natural", "perm"])
 def test_rmat_scale24(order):
     """R-MAT scale 24, edge factor 8, (0.55, 0.1, 0.1, 0.25): the full
