@@ -73,11 +73,15 @@ def apply_tuning(args, name, search):
     return {"source": "autotuner table", **{k: v for k, v in entry.items() if k not in ("trials",)}}
 
 
-def kernel_source_digest():
-    """Digest of the source of the single-graph kernels (k_inc_*, k_phase*),
-    which the stored counter traffic describes."""
+def kernel_source(workload):
+    """The source file of the kernels a workload's stored counter traffic
+    describes: the batch kernel, or the single-graph kernels."""
+    return "batch.hip" if WORKLOADS.get(workload, ("",))[0] == "batch" else "gcolor.hip"
+
+
+def kernel_source_digest(workload="rmat24"):
     h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_1205_3809_amd", "csrc", "gcolor.hip"), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1205_3809_amd", "csrc", kernel_source(workload)), "rb").read())
     return h.hexdigest()
 
 
@@ -91,7 +95,7 @@ def load_traffic_file(workload, order):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_sha256") != kernel_source_digest():
+    if d.get("kernel_source_sha256") != kernel_source_digest(workload):
         return None
     return d
 
@@ -128,7 +132,7 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings, out_
             if re.search(r"::k_\w+", name):
                 lib += val
                 calls += "k_zero_ctl" in name
-            m = re.search(r"k_(inc_[abc]|phase[12])", name)
+            m = re.search(r"k_(inc_[abc]|phase[12]|flow|batch)\b", name)
             if m:
                 key = m.group(1)
                 tot[key] = tot.get(key, 0.0) + val
@@ -140,7 +144,7 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings, out_
     gib_kib = 1024.0 * 1024.0
     fscale = gib_kib / fcopy if fcopy else None   # true read bytes / counted
     wscale = gib_kib / wcopy if wcopy else None
-    out = {"kernel_source_sha256": kernel_source_digest(), "workload": workload, "order": order,
+    out = {"kernel_source_sha256": kernel_source_digest(workload), "workload": workload, "order": order,
            "copy_calibration_kib": {"FETCH_SIZE": fcopy, "WRITE_SIZE": wcopy, "true_kib": gib_kib},
            "scale": {"FETCH_SIZE": fscale, "WRITE_SIZE": wscale}, "kernels": {}}
     if fcalls and wcalls:
@@ -440,14 +444,27 @@ def bench_batch(args):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         gc.color_graph_batch(vo, eo, rp, ci, V, nnz, None, out, ws, ticks, rounds)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
+    # the replays run on the current stream; HIP events on it time the launches
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
         graph.replay()
+    ev1.record()
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - w0) / args.steps
+    kms = ev0.elapsed_time(ev1) / args.steps
     khz = gc.wall_clock_khz()
     t = ticks.cpu().numpy().reshape(-1, 2).astype(np.float64)
     service_ms = (t[:, 1] - t[:, 0]) / khz
@@ -473,6 +490,10 @@ def bench_batch(args):
         cpu = {"value": round(sedges / tcpu, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
                "sample": "256 random graphs of the batch, one core, %.1f s" % tcpu, "parity_on_sample": ok}
     bmin = 4 * nnz + 8 * V  # read every row once, write every colour
+    traffic = load_traffic(args.workload, "natural", "batch", 1)
+    if traffic is not None:
+        traffic = {"hbm_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch": bmin,
+                   "GB_per_s": round(traffic / (kms / 1000.0) / 1e9, 1)}
     res = {
         "metric": "edges colored/sec, batched small graphs (one persistent launch)",
         "value": round(edges / (ms / 1000.0), 1), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
@@ -485,9 +506,11 @@ def bench_batch(args):
                          "completion_p50": round(float(np.percentile(done_ms, 50)), 4),
                          "completion_p99": round(float(np.percentile(done_ms, 99)), 4)},
         "rounds_max": int(rnd.max()), "rounds_mean": round(float(rnd.mean()), 2),
-        "roofline": {"kernel": "k_batch", "bound": "hbm", "achieved": round(bmin / (ms / 1000.0) / 1e9, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bmin / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_model": "lower bound: 4 B per row entry + 8 B per vertex"},
+        "roofline": {"kernel": "k_batch", "bound": "hbm", "achieved": round(bmin / (kms / 1000.0) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bmin / (kms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+                     "launch_ms_events": round(kms, 4), "traffic": traffic,
+                     "bytes_model": "lower bound: 4 B per row entry + 8 B per vertex"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
