@@ -119,7 +119,9 @@ size_t gcolor_workspace_bytes(int32_t n, int64_t nnz);
 /*
  * Colour the graph.  Uses a workspace the library allocates on first use and
  * keeps per device (grown when a larger graph arrives).  Returns 0 or a
- * negative GCOLOR_E* code.
+ * negative GCOLOR_E* code.  Every colouring call also keeps a 256-byte pinned
+ * host buffer per calling host thread for its small read-backs (held until
+ * the process ends).
  */
 int color_graph(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                 const uint32_t* priority, int32_t* colors_out, gcolor_stream_t stream);
