@@ -275,7 +275,7 @@ def main():
         elif args.engine == "dataflow":
             kinds = (("flow", gc.PROF_FLOW),)
         else:
-            kinds = (("inc_a", gc.PROF_INC_A), ("inc_b", gc.PROF_INC_B), ("inc_c", gc.PROF_INC_C))
+            kinds = (("inc_a", gc.PROF_INC_A), ("inc_c", gc.PROF_INC_C))
         for name, kid in kinds:
             ms, nl = gc.profile_read(kid)
             kern[name] = dict(total_ms=ms / args.steps, launches=nl // args.steps,

@@ -151,8 +151,10 @@ int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu);
 int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
 
 /*
- * Blocks per CU of the incremental engine's three round kernels (dirty
- * vertices, dirty-dirty counts, commits), 1..64 each, 0 = the common
+ * Blocks per CU of the incremental engine's round kernels: blocks_a for the
+ * dirty-vertex kernel, blocks_c for the commit kernel (which also completes
+ * the counters of dirty vertices with dirty preceding neighbours); blocks_b
+ * is checked and stored but no kernel uses it.  1..64 each, 0 = the common
  * blocks_per_cu above (the default).  Errors: GCOLOR_EINVAL outside 0..64.
  * Results never depend on it.
  */
@@ -179,7 +181,8 @@ int gcolor_get_batch_tuning(int32_t* block_threads, int32_t* lds_factor, int32_t
  * milliseconds and launch count of a kernel: 0 = plain phase 1 (tentative
  * colouring), 1 = plain phase 2 (conflict detection and worklist
  * compaction), 2 = incremental tentative colours of dirty vertices,
- * 3 = incremental conflict counters, 4 = incremental commit and push,
+ * 3 = (no kernel: the incremental counters are completed in 4),
+ * 4 = incremental counter completion, commit and push,
  * 5 = dataflow round.
  */
 int gcolor_profile(int32_t enable);

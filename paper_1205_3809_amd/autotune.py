@@ -6,7 +6,7 @@ colours of the starting setting (a mismatch raises).
 
 * Single graph (color_graph): the four degree-bin limits (one lane, 4 lanes,
   16 lanes and one wavefront per vertex; a workgroup above the last), the
-  blocks per CU of the round grids and of each round kernel, by coordinate
+  blocks per CU of the round grids and of the two round kernels, by coordinate
   descent from the current
   setting over candidate values, keeping a change only when it is faster by
   more than the noise margin.
@@ -85,6 +85,8 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     for _ in range(passes):
         changed = False
         for i in range(8):
+            if i == 6:
+                continue  # the second round kernel's blocks: no kernel uses them
             for v in (BIN_CANDIDATES[i] if i < 4 else BPC_CANDIDATES if i == 4 else KERNEL_BLOCK_CANDIDATES):
                 trial = list(cur)
                 trial[i] = v

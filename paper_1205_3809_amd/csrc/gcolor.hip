@@ -24,8 +24,9 @@
 //    Tentative colours of other vertices cannot change (their forbidden sets
 //    only grew by colours they do not hold), so rounds are the plain engine's,
 //    vertex for vertex.  Kernels per round: k_inc_a (first-fit of dirty
-//    vertices), k_inc_b (counter recount and updates, candidate list), k_inc_c
-//    (commit of candidates whose counter is 0, dirty marks to neighbours).
+//    vertices, counter recount and updates, candidate list) and k_inc_c
+//    (counters completed for dirty vertices with dirty preceding neighbours,
+//    commit of candidates whose counter is 0, dirty marks to neighbours).
 //    A committed vertex's tentative colour is set to 0, so one gather of a
 //    neighbour's tentative colour tells both "uncoloured" and "same colour".
 //
@@ -523,19 +524,20 @@ __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
 //            clean neighbours holding the old or the new colour get their
 //            counters adjusted by -1 / +1.  Dirty neighbours are recognised
 //            in a one-bit-per-vertex bitmap (L2 resident).  A dirty vertex
-//            with a preceding dirty neighbour goes to k_inc_b.
-//   k_inc_b  adds, for those, the preceding dirty neighbours holding the
-//            same new colour (their new colours are final now).
-//   k_inc_c  commits every candidate whose counter is 0 and marks dirty
-//            each later neighbour holding the same tentative colour (a
-//            preceding one cannot: it would have kept the counter above 0).
+//            with a preceding dirty neighbour joins the candidate list as ~w.
+//   k_inc_c  completes, for each ~w, the counter with the preceding dirty
+//            neighbours holding w's new colour (final since k_inc_a; one
+//            committed in this kernel shows -t, so the count takes |word|);
+//            then commits every candidate whose counter is 0 and marks
+//            dirty each later neighbour holding the same tentative colour
+//            (a preceding one cannot: it would have kept the counter above
+//            0).
 // List sets: dirty lists rotate over 3 sets (k % 3) with their bitmaps, so
 // the bits of round k-1 can be cleared during round k; candidate lists
-// alternate over 2 sets; one set holds the k_inc_b list.
+// alternate over 2 sets.
 // ===========================================================================
 
 constexpr int kSetCand = 3;  // + (k & 1)
-constexpr int kSetB = 5;
 
 __host__ __device__ inline int dlist(int k) { return k % 3; }
 __host__ __device__ inline int cset(int k) { return kSetCand + (k & 1); }
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
     stage_init(&stg);
     S* st = static_cast<S*>(a.st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int t = 0; t < kSetB + 1; ++t)
+        for (int t = 0; t < kSets; ++t)
             if (t != cset(1))
                 for (int b = 0; b < 8; ++b) a.ctl->cnt[t][b] = 0;
         for (int i = 0; i < kLogW; ++i) a.log[i] = 0;
@@ -717,7 +719,7 @@ __device__ __forceinline__ int first_fit_long(const int* __restrict__ colp, cons
 // toward w's counter; later clean neighbours holding old / now get -1 / +1
 // (returns true when such a counter just reached 0 for the first time in
 // this round: x becomes a candidate).  Dirty neighbours are skipped; a
-// preceding one sets *dlow (k_inc_b finishes w's count).
+// preceding one sets *dlow (k_inc_c finishes w's count).
 __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __restrict__ bits, int k, int w, int p,
                                            int lim, int now, int old, int x, int sx, int* cnt, bool* dlow) {
     if (p < lim) {
@@ -976,14 +978,15 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, co
 
 // Dirty vertex w handled by a group of GS lanes (GS = kBlock: the whole
 // workgroup, with LDS for the reductions).  Returns via the stage: w itself
-// to the k_inc_b list or, when its count is final and 0, to the candidates.
+// to the candidate list, as ~w while preceding dirty neighbours leave its
+// count open, as w when the count is final and 0.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg,
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
                                              long long* dedges);
 
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* stgb, int k, int w, int lig,
+__device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, int w, int lig,
                                              uint64_t* red, int* shc, unsigned* ffbm, int* cc, long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
@@ -997,7 +1000,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
             bool dlow;
             int len;
             inc_a_heavy<GS, S>(a, stg, k, w, s, old, lig, red, shc, bm, cc, &now, &cnt, &dlow, &len);
-            inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, len, lig, now, cnt, dlow, shc, dedges);
+            inc_a_finish<GS, S>(a, stg, k, w, e - s, len, lig, now, cnt, dlow, shc, dedges);
             return;
         }
     }
@@ -1057,13 +1060,13 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, Stage* s
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
-    inc_a_finish<GS, S>(a, stg, stgb, k, w, e - s, e - s, lig, now, cnt, dlow, shc, dedges);
+    inc_a_finish<GS, S>(a, stg, k, w, e - s, e - s, lig, now, cnt, dlow, shc, dedges);
 }
 
 // Group totals of the counter and the preceding-dirty flag; state, counter
 // and list appends of dirty vertex w.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* stgb, int k, int w, int deg,
+__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
                                              long long* dedges) {
     S* st = static_cast<S*>(a.st);
@@ -1094,17 +1097,16 @@ __device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, Stage* s
         cand = !to_b && cnt == 0 && (atomicExch(&a.cflag[w], k) != k);
     }
     if (GS == kBlock && threadIdx.x >= kWave) return;
-    stage_append(a, stgb, to_b, w, deg, kSetB);
-    stage_append(a, stg, cand, w, deg, cs);
+    stage_append(a, stg, to_b || cand, to_b ? ~w : w, deg, cs);
 }
 
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, Stage* stgb, int k, const int* list, int cnt,
+__device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt,
                                             int local, unsigned* ffbm, long long* dedges) {
     constexpr int CV = kBlock / GS;
     const int lig = threadIdx.x & (GS - 1);
     const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, stgb, k, list[idx], lig, nullptr, nullptr, ffbm, nullptr, dedges);
+    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, k, list[idx], lig, nullptr, nullptr, ffbm, nullptr, dedges);
 }
 
 // Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
@@ -1114,9 +1116,13 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
     __shared__ uint64_t red[kBlock / kWave];
     __shared__ int shc[8];
     __shared__ Stage stg;
-    __shared__ Stage stgb;
     __shared__ unsigned ffbm[(kBlock / kWave) * kFFWords];
     __shared__ int cc[2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the list that this round's commits fill (round k-2's dirty list,
+        // whose bitmap words k_inc_a of round k-1 cleared)
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[dlist(k + 1)][b] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0 && k - 1 < kMaxLog) {
         long long nd = 0;
         for (int b = 0; b < kBins; ++b) nd += a.ctl->cnt[dlist(k)][b];
@@ -1143,29 +1149,26 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
         }
     }
     stage_init(&stg);
-    stage_init(&stgb);
     long long dedges[2] = {0, 0};  // degree sum and scanned entries of the dirty rows
-#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, &stgb, k, L, C, LOC, ffbm, dedges)
-#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, &stgb, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, dedges)
-#define A_AFTER()                                \
-    {                                            \
-        stage_maybe_flush(a, &stg, cset(k));     \
-        stage_maybe_flush(a, &stgb, kSetB);      \
-    }
+#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, k, L, C, LOC, ffbm, dedges)
+#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, dedges)
+#define A_AFTER() stage_maybe_flush(a, &stg, cset(k))
     GC_WALK_CHUNKS(a, m, dlist(k), A_GS, A_BLOCK, A_AFTER)
 #undef A_GS
 #undef A_BLOCK
 #undef A_AFTER
     stage_flush(a, &stg, cset(k));
-    stage_flush(a, &stgb, kSetB);
     if (k - 1 < kMaxLog) {
         block_add_log(dedges[0], &a.log[kLogW * (k - 1) + 3]);
         block_add_log(dedges[1], &a.log[kLogW * (k - 1) + 4]);
     }
 }
 
-// Round k, kernel B: for dirty vertices with preceding dirty neighbours, add
-// those holding the same (final) new colour to the counter.
+// Preceding dirty neighbours of w (entries start, start + STRIDE, ... < lim
+// of row) holding colour now: dirty vertices are uncoloured at the start of
+// the round, and one committed during the commit kernel shows -now, so the
+// count compares |word| (both ways the neighbour keeps w from committing
+// with now).
 template <int STRIDE, typename S>
 __device__ __forceinline__ int inc_b_count(const int* __restrict__ row, const S* __restrict__ st,
                                            const unsigned* __restrict__ bits, int w, int start, int lim, int now) {
@@ -1182,90 +1185,12 @@ __device__ __forceinline__ int inc_b_count(const int* __restrict__ row, const S*
         for (int j = 0; j < 4; ++j) d[j] = (p0 + j * STRIDE < lim) && is_dirty(bits, x[j]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (d[j]) c += ((int)st[x[j]] == now);
+            if (d[j]) {
+                const int sx = st[x[j]];
+                c += ((sx < 0 ? -sx : sx) == now);
+            }
     }
     return c;
-}
-
-template <int GS, typename S>
-__device__ __forceinline__ void inc_b_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local) {
-    constexpr int CV = kBlock / GS;
-    const S* st = static_cast<const S*>(a.st);
-    const int lig = threadIdx.x & (GS - 1);
-    const int idx = local * CV + (int)threadIdx.x / GS;
-    bool cand = false;
-    int w = 0, deg = 0;
-    if (idx < cnt) {
-        w = list[idx];
-        const int s = a.row_ptr[w];
-        deg = a.row_ptr[w + 1] - s;
-        const int now = st[w];
-        const int* row = a.colp;
-        int lim = s + a.split[w];
-        if constexpr (GS == kWave) {
-            if (deg > kHeavyDeg) {  // preceding segment of the active row
-                const HeavyView hv = heavy_view(a, w, s);
-                row = hv.row;
-                lim = s + hv.pa;
-            }
-        }
-        int c = inc_b_count<GS, S>(row, st, dbits(a, k), w, s + lig, lim, now);
-        c = group_sum<GS>(c);
-        if (lig == 0) {
-            const int tot = a.conf[w] + c;
-            a.conf[w] = tot;
-            cand = tot == 0 && (atomicExch(&a.cflag[w], k) != k);
-        }
-    }
-    stage_append(a, stg, cand, w, deg, cset(k));
-}
-
-template <typename S>
-__device__ __forceinline__ void inc_b_block(const Args& a, Stage* stg, int k, int w, int* sh) {
-    const S* st = static_cast<const S*>(a.st);
-    const int s = a.row_ptr[w], deg = a.row_ptr[w + 1] - s;
-    const int now = st[w];
-    const int* row = a.colp;
-    int lim = s + a.split[w];
-    if (deg > kHeavyDeg) {  // preceding segment of the active row
-        const HeavyView hv = heavy_view(a, w, s);
-        row = hv.row;
-        lim = s + hv.pa;
-    }
-    int c = inc_b_count<kBlock, S>(row, st, dbits(a, k), w, s + (int)threadIdx.x, lim, now);
-    c = group_sum<kWave>(c);
-    if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
-    __syncthreads();
-    const int tot = sh[0] + sh[1] + sh[2] + sh[3];
-    __syncthreads();
-    bool cand = false;
-    if (threadIdx.x == 0) {
-        const int t = a.conf[w] + tot;
-        a.conf[w] = t;
-        cand = t == 0 && (atomicExch(&a.cflag[w], k) != k);
-    }
-    if (threadIdx.x < kWave) stage_append(a, stg, cand, w, deg, cset(k));
-}
-
-// Also clears the list that round k+1's commits fill (round k-2's dirty list,
-// whose bits k_inc_a of round k-1 cleared).
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_inc_b(Args a, int k) {
-    __shared__ int sh[kBlock / kWave];
-    __shared__ Stage stg;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int b = 0; b < 8; ++b) a.ctl->cnt[dlist(k + 1)][b] = 0;
-    const ChunkMap m = make_map(a.ctl, kSetB);
-    if ((int)blockIdx.x >= m.total) return;
-    stage_init(&stg);
-#define B_GS(GS, L, C, LOC) inc_b_chunk<GS, S>(a, &stg, k, L, C, LOC)
-#define B_BLOCK(V) inc_b_block<S>(a, &stg, k, (V), sh)
-#define B_AFTER() stage_maybe_flush(a, &stg, cset(k))
-    GC_WALK_CHUNKS(a, m, kSetB, B_GS, B_BLOCK, B_AFTER)
-#undef B_GS
-#undef B_BLOCK
-#undef B_AFTER
-    stage_flush(a, &stg, cset(k));
 }
 
 // Dirty mark from a committed vertex v (colour t) to a later row entry u
@@ -1306,6 +1231,9 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
     }
 }
 
+// One entry of the candidate list: a candidate v (>= 0) commits if its
+// counter is 0; ~w (a dirty vertex with preceding dirty neighbours) first
+// has its counter completed (inc_b_count) and commits if the total is 0.
 template <int GS, typename S>
 __device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local,
                                             long long* ncom, long long* ndeg) {
@@ -1314,10 +1242,29 @@ __device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, co
     const int lig = threadIdx.x & (GS - 1);
     const int idx = local * CV + (int)threadIdx.x / GS;
     if (idx < cnt) {
-        const int v = list[idx];
+        const int ent = list[idx];
+        const int v = ent < 0 ? ~ent : ent;
         const int t = st[v];
-        if (a.conf[v] == 0 && t > 0) {
-            const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+        const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+        bool commit;
+        if (ent < 0) {
+            const int* row = a.colp;
+            int lim = s + a.split[v];
+            if constexpr (GS == kWave) {
+                if (e - s > kHeavyDeg) {  // preceding segment of the active row
+                    const HeavyView hv = heavy_view(a, v, s);
+                    row = hv.row;
+                    lim = s + hv.pa;
+                }
+            }
+            const int c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
+            const int tot = a.conf[v] + c;  // every lane reads before lane 0 writes (one wavefront)
+            if (lig == 0) a.conf[v] = tot;
+            commit = tot == 0;
+        } else {
+            commit = a.conf[v] == 0 && t > 0;
+        }
+        if (commit) {
             const int* row = a.colp;
             int start = s + a.split[v], end = e;
             if constexpr (GS == kWave) {
@@ -1341,12 +1288,30 @@ __device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, co
 }
 
 template <typename S>
-__device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, int v, long long* ncom,
+__device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, int ent, int* sh, long long* ncom,
                                             long long* ndeg) {
     S* st = static_cast<S*>(a.st);
+    const int v = ent < 0 ? ~ent : ent;
     const int t = st[v];
-    if (a.conf[v] != 0 || t <= 0) return;  // block-uniform: only this block writes them in this kernel
     const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+    if (ent < 0) {
+        const int* row = a.colp;
+        int lim = s + a.split[v];
+        if (e - s > kHeavyDeg) {  // preceding segment of the active row
+            const HeavyView hv = heavy_view(a, v, s);
+            row = hv.row;
+            lim = s + hv.pa;
+        }
+        const int c = group_sum<kWave>(inc_b_count<kBlock, S>(row, st, dbits(a, k), v, s + (int)threadIdx.x, lim, t));
+        if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
+        __syncthreads();
+        const int tot = a.conf[v] + sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();  // every thread has read conf[v] and sh
+        if (threadIdx.x == 0) a.conf[v] = tot;
+        if (tot != 0) return;  // block-uniform
+    } else if (a.conf[v] != 0 || t <= 0) {
+        return;  // block-uniform: only this block writes them in this kernel
+    }
     const int* row = a.colp;
     int start = s + a.split[v], end = e;
     if (e - s > kHeavyDeg) {  // later segment of the active row
@@ -1367,16 +1332,13 @@ __device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, in
 }
 
 // Round k, kernel C: commit every candidate whose counter is 0, mark its
-// dirty neighbours for round k+1.  Clears the candidate list of round k+1 and
-// the k_inc_b list.
+// dirty neighbours for round k+1.  Clears the candidate list of round k+1.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
     __shared__ Stage stg;
+    __shared__ int sh[kBlock / kWave];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int b = 0; b < 8; ++b) {
-            a.ctl->cnt[cset(k + 1)][b] = 0;
-            a.ctl->cnt[kSetB][b] = 0;
-        }
+        for (int b = 0; b < 8; ++b) a.ctl->cnt[cset(k + 1)][b] = 0;
         if (k < kMaxLog) {  // round k+1's dirty degree sum and scanned entries
             a.log[kLogW * k + 3] = 0;
             a.log[kLogW * k + 4] = 0;
@@ -1388,7 +1350,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
     long long ncom = 0, ndeg = 0;
     const int ds = dlist(k + 1);
 #define C_GS(GS, L, C, LOC) inc_c_chunk<GS, S>(a, &stg, k, L, C, LOC, &ncom, &ndeg)
-#define C_BLOCK(V) inc_c_block<S>(a, &stg, k, (V), &ncom, &ndeg)
+#define C_BLOCK(V) inc_c_block<S>(a, &stg, k, (V), sh, &ncom, &ndeg)
 #define C_AFTER() stage_maybe_flush(a, &stg, ds)
     GC_WALK_CHUNKS(a, m, cset(k), C_GS, C_BLOCK, C_AFTER)
 #undef C_GS
@@ -1901,7 +1863,7 @@ std::vector<DeviceCache> g_dev;
 // Process-wide tuning: degree-bin limits and blocks per CU of the grids.
 int g_bins[4] = {8, 32, 128, 2048};
 int g_blocks_per_cu = 4;
-// blocks per CU of k_inc_a, k_inc_b, k_inc_c (0: g_blocks_per_cu)
+// blocks per CU of k_inc_a, (unused), k_inc_c (0: g_blocks_per_cu)
 int g_kernel_blocks[3] = {0, 0, 0};
 
 // Optional per-kernel timing with HIP events recorded around each launch.
@@ -2059,7 +2021,6 @@ int inc_rounds(const Args& a, int64_t n, const int* grid, Launcher& L, int32_t* 
         const int nb = std::min(*batch, last - k + 1);
         for (int j = 0; j < nb; ++j, ++k) {
             GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid[0], kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncB, [&] { k_inc_b<S><<<grid[1], kBlock, 0, st>>>(a, k); }));
             GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid[2], kBlock, 0, st>>>(a, k); }));
         }
         // dirty list of the next round k: empty exactly when every vertex is committed
