@@ -264,7 +264,7 @@ def get_batch_tuning():
 PROF_PHASE1 = 0   # plain engine: tentative colouring
 PROF_PHASE2 = 1   # plain engine: conflict detection + compaction
 PROF_INC_A = 2    # incremental: tentative colours of dirty vertices
-PROF_INC_B = 3    # incremental: conflict counters, candidates
+PROF_INC_B = 3    # no kernel (the incremental counters are completed in PROF_INC_C)
 PROF_INC_C = 4    # incremental: commit + push
 PROF_FLOW = 5     # dataflow: one round
 
