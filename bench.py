@@ -79,10 +79,21 @@ def kernel_source(workload):
     return "batch.hip" if WORKLOADS.get(workload, ("",))[0] == "batch" else "gcolor.hip"
 
 
+def code_digest(text):
+    """Digest of HIP source text without its comments and with whitespace
+    runs folded: comment edits leave it unchanged, code edits do not."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = re.sub(r"\s+", " ", text).strip()
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def kernel_source_digest(workload="rmat24"):
-    h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_1205_3809_amd", "csrc", kernel_source(workload)), "rb").read())
-    return h.hexdigest()
+    """Code digest of the kernel source a workload's counter traffic was
+    taken on (stored with the traffic; the traffic is used only while the
+    current source has the same digest)."""
+    return code_digest(open(os.path.join(ROOT, "paper_1205_3809_amd", "csrc", kernel_source(workload))).read())
 
 
 def load_traffic_file(workload, order):

@@ -27,8 +27,13 @@
 //    vertices, counter recount and updates, candidate list) and k_inc_c
 //    (counters completed for dirty vertices with dirty preceding neighbours,
 //    commit of candidates whose counter is 0, dirty marks to neighbours).
-//    A committed vertex's tentative colour is set to 0, so one gather of a
-//    neighbour's tentative colour tells both "uncoloured" and "same colour".
+//    A vertex's state word holds its tentative colour while it is uncoloured
+//    and minus its colour once committed, so one gather of a neighbour's word
+//    answers both "committed, with which colour" and "same tentative colour".
+//
+// A third engine computes a different function: the dataflow algorithm
+// (Algorithm 3) in rounds (GCOLOR_DATAFLOW; k_flow_seed, k_flow), whose result
+// is the serial first-fit in (priority, id) order.
 //
 // Degree bins (the vertex-to-lane mapping of every row-scanning kernel):
 //   bin 0: one lane per vertex         bin 1: 4 lanes per vertex
