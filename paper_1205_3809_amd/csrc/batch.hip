@@ -13,15 +13,16 @@
 // neighbours' counters, and candidates whose counter is 0 commit.
 //
 // Lanes: groups of 8 lanes per vertex (the stencil and geometric graphs of a
-// batch have degrees of a few to a few tens), eight row entries per lane
-// kept in registers between the first-fit and the counter pass; longer rows
-// are re-gathered.
+// batch have degrees of a few to a few tens; 4 in the LDS path for lists
+// longer than one pass), row entries kept in registers between the
+// first-fit and the counter pass; longer rows are re-gathered.
 //
 // Graphs of at most nl vertices (nl is set per launch from the batch's mean
 // graph size, at most 65536) and maximum degree at most 126 keep their
 // per-vertex state in LDS (see color_one_lds); the others use global memory.
-// Per-graph start/end times come from the constant-rate wall clock.  No host synchronisation and no allocation happen inside the
-// call, so it can be captured in a HIP graph.
+// Per-graph start/end times come from the constant-rate wall clock.  No host
+// synchronisation and no allocation happen inside the call, so it can be
+// captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
