@@ -361,6 +361,28 @@ def main():
             "plain_method_bytes": int(b_plain), "plain_method_GBps": round(b_plain / step_s / 1e9, 1),
             "plain_method_frac": round(b_plain / step_s / 1e9 / HBM_PEAK_GBS, 4),
             "floor_bytes": int(b_min), "floor_GBps": round(b_min / step_s / 1e9, 1)}
+        if args.engine == "incremental":
+            # the gather ceiling of this graph: one byte gathered per row entry
+            # through the graph's own col_idx (torch indexing of an n-byte
+            # array), against the row entries k_inc_a reads per second
+            st8 = torch.zeros(g.n, dtype=torch.uint8, device=dev)
+            st8[ci]
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                st8[ci]
+            e1.record()
+            torch.cuda.synchronize()
+            probe = g.nnz / (e0.elapsed_time(e1) / 5 / 1e3)
+            scanned = sum(d[3] for d in st.detail)
+            krate = scanned / (kern["inc_a"]["total_ms"] / 1e3)
+            roofline["gather"] = {
+                "kernel": "inc_a", "entries_per_s": round(krate / 1e9, 2), "probe_entries_per_s": round(probe / 1e9, 2),
+                "unit": "G entries/s", "frac": round(krate / probe, 3),
+                "probe": "torch indexing of an n-byte array by the graph's col_idx (one byte per row entry)"}
+            del st8
         log("kernels: %s" % json.dumps(roofline["kernels"]))
 
     # CPU oracle on the same workload, and serial greedy for the colour count
