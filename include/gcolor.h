@@ -63,7 +63,7 @@ enum {
     GCOLOR_ECSR = -2,       /* malformed CSR (reported only with GCOLOR_VALIDATE) */
     GCOLOR_EWORKSPACE = -3, /* caller workspace smaller than gcolor_workspace_bytes */
     GCOLOR_EHIP = -4,       /* a HIP runtime call failed */
-    GCOLOR_EROUNDS = -5,    /* round cap exceeded (never happens for valid input) */
+    GCOLOR_EROUNDS = -5,    /* round cap exceeded (only with a cap below the default) */
     GCOLOR_ENOTSUP = -6,    /* sizes beyond what the library supports */
     GCOLOR_EINTERNAL = -7   /* an internal consistency check failed (a bug; report it) */
 };
@@ -160,6 +160,21 @@ int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
  */
 int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_b, int32_t blocks_c);
 int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* blocks_c);
+
+/*
+ * Round cap (process-wide, applies to later color_graph / color_graph_ex
+ * calls of every engine): a call that needs more than max_rounds rounds
+ * stops launching after round max_rounds and returns GCOLOR_EROUNDS, with
+ * colors_out and *stats undefined.  A call that needs at most max_rounds
+ * rounds is unaffected.  0 restores the default, n + 64 for a graph of n
+ * vertices: every engine ends within n rounds on valid input (the vertex
+ * with the smallest key among those left is committed in every round of
+ * Algorithm 2; the dataflow rounds follow increasing paths of the order), so
+ * the default is never reached and GCOLOR_EROUNDS then signals a bug.
+ * Errors: GCOLOR_EINVAL for max_rounds < 0.
+ */
+int gcolor_set_round_cap(int32_t max_rounds);
+int gcolor_get_round_cap(int32_t* max_rounds);
 
 /*
  * Batch tuning (process-wide, applies to later color_graph_batch calls).

@@ -29,6 +29,8 @@ from ._binding import (  # noqa: F401
     set_batch_tuning,
     get_kernel_blocks,
     set_kernel_blocks,
+    get_round_cap,
+    set_round_cap,
     profile,
     profile_read,
     raw_library,

@@ -77,6 +77,10 @@ def _load():
     lib.gcolor_set_kernel_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.gcolor_set_kernel_blocks.restype = ctypes.c_int
     lib.gcolor_get_kernel_blocks.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
+    lib.gcolor_set_round_cap.argtypes = [ctypes.c_int32]
+    lib.gcolor_set_round_cap.restype = ctypes.c_int
+    lib.gcolor_get_round_cap.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.gcolor_get_round_cap.restype = ctypes.c_int
     lib.gcolor_set_batch_tuning.restype = ctypes.c_int
     lib.gcolor_get_batch_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.gcolor_get_tuning.restype = ctypes.c_int
@@ -244,6 +248,20 @@ def get_kernel_blocks():
     v = [ctypes.c_int32() for _ in range(3)]
     _lib.gcolor_get_kernel_blocks(*[ctypes.byref(x) for x in v])
     return tuple(int(x.value) for x in v)
+
+
+def set_round_cap(max_rounds: int = 0) -> None:
+    """Most rounds a later colouring may take (0: the default, n + 64);
+    a colouring that needs more raises GColorError with code -5."""
+    rc = _lib.gcolor_set_round_cap(int(max_rounds))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_set_round_cap")
+
+
+def get_round_cap() -> int:
+    v = ctypes.c_int32()
+    _lib.gcolor_get_round_cap(ctypes.byref(v))
+    return int(v.value)
 
 
 def set_batch_tuning(block_threads: int = 0, lds_factor: int = 8, lds_max_vertices: int = 65536) -> None:

@@ -1870,6 +1870,15 @@ int g_bins[4] = {8, 32, 128, 2048};
 int g_blocks_per_cu = 4;
 // blocks per CU of k_inc_a, (unused), k_inc_c (0: g_blocks_per_cu)
 int g_kernel_blocks[3] = {0, 0, 0};
+// Most rounds a call may take (0: n + 64).  Every engine ends within n
+// rounds on valid input, so the default is never reached; a smaller cap
+// exercises the GCOLOR_EROUNDS path.
+int g_round_cap = 0;
+
+int64_t round_limit(int64_t n) {
+    std::lock_guard<std::mutex> g(g_mu);
+    return g_round_cap > 0 ? g_round_cap : n + 64;
+}
 
 // Optional per-kernel timing with HIP events recorded around each launch.
 enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfFlow = 5, kProfKinds = 6 };
@@ -1997,33 +2006,39 @@ int sum_counts(const int32_t* h) {
     return t;
 }
 
-int run_plain(const Args& a, int64_t n, int grid, Launcher& L, int32_t* host, hipStream_t st) {
-    int k = 0;
+// Batches end at the round cap, so a colouring returns GCOLOR_EROUNDS
+// exactly when it needs more rounds than the cap.
+int run_plain(const Args& a, int64_t limit, int grid, Launcher& L, int32_t* host, hipStream_t st) {
+    int64_t k = 0;
     int batch = 4;
     for (;;) {
-        for (int j = 0; j < batch; ++j, ++k) {
-            const int side = k & 1;
-            GC_CHECK(L(kProfPhase1, [&] { k_phase1<<<grid, kBlock, 0, st>>>(a, side, k); }));
-            GC_CHECK(L(kProfPhase2, [&] { k_phase2<<<grid, kBlock, 0, st>>>(a, side, k); }));
+        const int64_t nb = std::min<int64_t>(batch, limit - k);
+        for (int64_t j = 0; j < nb; ++j, ++k) {
+            const int side = (int)(k & 1), kk = (int)k;
+            GC_CHECK(L(kProfPhase1, [&] { k_phase1<<<grid, kBlock, 0, st>>>(a, side, kk); }));
+            GC_CHECK(L(kProfPhase2, [&] { k_phase2<<<grid, kBlock, 0, st>>>(a, side, kk); }));
         }
+        // worklist of round k (0-based), the next to run
         GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[k & 1][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
         GC_CHECK(hipStreamSynchronize(st));
         if (sum_counts(host) == 0) return GCOLOR_OK;
-        if (k > n + 64) return GCOLOR_EROUNDS;
+        if (k >= limit) return GCOLOR_EROUNDS;
         batch = std::min(batch * 2, 16);
     }
 }
 
-// Rounds *k, *k + 1, ... up to round `last` (inclusive) or the end, in
-// batches between host checks; *done when the next round's dirty list is
-// empty (every vertex committed).
+// Rounds *k, *k + 1, ... up to round `last` (inclusive, at most `limit`)
+// or the end, in batches between host checks; *done when the next round's
+// dirty list is empty (every vertex committed).  GCOLOR_EROUNDS when rounds
+// 1..limit have run and a vertex is left.
 template <typename S>
-int inc_rounds(const Args& a, int64_t n, const int* grid, Launcher& L, int32_t* host, hipStream_t st, int* kio, int last,
-               int* batch, bool* done) {
+int inc_rounds(const Args& a, int64_t limit, const int* grid, Launcher& L, int32_t* host, hipStream_t st, int* kio,
+               int last, int* batch, bool* done) {
     int k = *kio;
     *done = false;
-    while (k <= last) {
-        const int nb = std::min(*batch, last - k + 1);
+    last = (int)std::min<int64_t>(last, limit);
+    for (;;) {
+        const int nb = std::max(0, std::min(*batch, last - k + 1));
         for (int j = 0; j < nb; ++j, ++k) {
             GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid[0], kBlock, 0, st>>>(a, k); }));
             GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid[2], kBlock, 0, st>>>(a, k); }));
@@ -2036,27 +2051,32 @@ int inc_rounds(const Args& a, int64_t n, const int* grid, Launcher& L, int32_t* 
             *done = true;
             return GCOLOR_OK;
         }
-        if (k > n + 64) return GCOLOR_EROUNDS;
+        if (k > limit) return GCOLOR_EROUNDS;
+        if (k > last) return GCOLOR_OK;
         *batch = std::min(*batch * 2, 16);
     }
-    return GCOLOR_OK;
 }
 
 // Dataflow rounds in batches between host checks (the batch grows to 256
 // rounds: a natural-order graph can need tens of thousands).
-int run_dataflow(const Args& a, int64_t n, int vgrid, int grid, bool natural, Launcher& L, int32_t* host,
-                 hipStream_t st) {
+int run_dataflow(const Args& a, int64_t n, int64_t limit, int vgrid, int grid, bool natural, Launcher& L,
+                 int32_t* host, hipStream_t st) {
     k_flow_seed<<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
-    int k = 1, batch = 4;
+    int64_t k = 1;
+    int batch = 4;
     for (;;) {
-        for (int j = 0; j < batch; ++j, ++k)
-            GC_CHECK(L(kProfFlow, [&] { k_flow<<<grid, kBlock, 0, st>>>(a, k); }));
+        const int64_t nb = std::min<int64_t>(batch, limit - k + 1);
+        for (int64_t j = 0; j < nb; ++j, ++k) {
+            const int kk = (int)k;
+            GC_CHECK(L(kProfFlow, [&] { k_flow<<<grid, kBlock, 0, st>>>(a, kk); }));
+        }
         // round k's list (the next to run): empty once nothing is left to release
-        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[fset(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[fset((int)k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost,
+                                st));
         GC_CHECK(hipStreamSynchronize(st));
         if (sum_counts(host) == 0) break;
-        if (k > n + 64) return GCOLOR_EROUNDS;
+        if (k > limit) return GCOLOR_EROUNDS;
         batch = std::min(batch * 2, 256);
     }
     unsigned long long coloured = 0;
@@ -2076,15 +2096,15 @@ __global__ __launch_bounds__(kBlock) void k_widen(int n, const int8_t* __restric
 // a signed byte: the engine starts with 8-bit state words (half the bytes of
 // the gathers that dominate every kernel) and, if round 128 is reached,
 // widens them to 16 bits (32 when max degree + 1 exceeds 32767).
-int run_incremental(Args a, int64_t n, int vgrid, const int* grid, bool natural, void* wide_slot, Launcher& L,
-                    int32_t* host, hipStream_t st) {
+int run_incremental(Args a, int64_t n, int64_t limit, int vgrid, const int* grid, bool natural, void* wide_slot,
+                    Launcher& L, int32_t* host, hipStream_t st) {
     constexpr int kLast8 = 127;
     k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
     GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid[2], kBlock, 0, st>>>(a, 1); }));
     int k = 2, batch = 4;
     bool done = false;
-    int rc = inc_rounds<int8_t>(a, n, grid, L, host, st, &k, kLast8, &batch, &done);
+    int rc = inc_rounds<int8_t>(a, limit, grid, L, host, st, &k, kLast8, &batch, &done);
     if (rc) return rc;
     if (!done) {
         k_maxdeg<<<vgrid, kBlock, 0, st>>>((int)n, a.row_ptr, a.ctl);
@@ -2096,11 +2116,11 @@ int run_incremental(Args a, int64_t n, int vgrid, const int* grid, bool natural,
         if (host[0] + 1 <= 32767) {
             k_widen<int16_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int16_t*>(wide_slot));
             GC_CHECK(hipGetLastError());
-            rc = inc_rounds<int16_t>(a, n, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+            rc = inc_rounds<int16_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
         } else {
             k_widen<int32_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int32_t*>(wide_slot));
             GC_CHECK(hipGetLastError());
-            rc = inc_rounds<int32_t>(a, n, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+            rc = inc_rounds<int32_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
         }
         if (rc) return rc;
     }
@@ -2176,17 +2196,18 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     thread_local EventPairs evp;
     evp.used = 0;
     Launcher L{st, g_prof, &evp};
+    const int64_t limit = round_limit(n);
     int rc;
     if (plain) {
         if (natural) {
             k_setup_natural<<<vgrid, kBlock, 0, st>>>(a, a.split);
             GC_CHECK(hipGetLastError());
         }
-        rc = run_plain(a, n, grid, L, host, st);
+        rc = run_plain(a, limit, grid, L, host, st);
     } else if (flow) {
-        rc = run_dataflow(a, n, vgrid, grid, natural, L, host, st);
+        rc = run_dataflow(a, n, limit, vgrid, grid, natural, L, host, st);
     } else {
-        rc = run_incremental(a, n, vgrid, kgrid, natural, base + Lw.told, L, host, st);
+        rc = run_incremental(a, n, limit, vgrid, kgrid, natural, base + Lw.told, L, host, st);
     }
     if (rc) return rc;
 
@@ -2362,6 +2383,19 @@ int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* bloc
     if (blocks_a) *blocks_a = g_kernel_blocks[0];
     if (blocks_b) *blocks_b = g_kernel_blocks[1];
     if (blocks_c) *blocks_c = g_kernel_blocks[2];
+    return GCOLOR_OK;
+}
+
+int gcolor_set_round_cap(int32_t max_rounds) {
+    if (max_rounds < 0) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_round_cap = max_rounds;
+    return GCOLOR_OK;
+}
+
+int gcolor_get_round_cap(int32_t* max_rounds) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (max_rounds) *max_rounds = g_round_cap;
     return GCOLOR_OK;
 }
 

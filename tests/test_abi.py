@@ -98,6 +98,21 @@ def test_tuning_validation():
     assert gc.get_tuning() == (old, bpc)
 
 
+def test_round_cap_roundtrip_and_range():
+    import paper_1205_3809_amd as gc
+    old = gc.get_round_cap()
+    try:
+        gc.set_round_cap(7)
+        assert gc.get_round_cap() == 7
+        with pytest.raises(gc.GColorError) as e:
+            gc.set_round_cap(-1)
+        assert e.value.code == -1 and gc.get_round_cap() == 7
+        gc.set_round_cap(0)
+        assert gc.get_round_cap() == 0
+    finally:
+        gc.set_round_cap(old)
+
+
 def test_batch_tuning_roundtrip_and_range():
     import paper_1205_3809_amd as gc
     old = gc.get_batch_tuning()

@@ -321,6 +321,44 @@ def test_validate_rejects_malformed_csr():
     assert np.array_equal(out.cpu().numpy(), oracle.spec_sim(rp, ci).colors)
 
 
+@pytest.mark.parametrize("flags,name", [(0, "incremental"), (4, "plain"), (8, "dataflow")])
+def test_round_cap_forced_from_the_host(flags, name):
+    """A cap below the rounds a colouring needs returns GCOLOR_EROUNDS (-5)
+    for every engine; a cap equal to them, or above, colours as without a
+    cap.  The graphs need 1, a few tens and 151 to 300 rounds (the
+    incremental engine widens its state words after round 127; caps of 127
+    and 128 stop it on either side of that step)."""
+    import paper_1205_3809_amd as gc
+    cases = [graphgen.empty(50), rmat(12, 8, (0.55, 0.1, 0.1), 3), graphgen.path(300)]
+    assert gc.get_round_cap() == 0
+    try:
+        for g in cases:
+            print("case round-cap engine=%s n=%d" % (name, g.n), flush=True)
+            ref, st = gpu_color(g, flags=flags)
+            need = st.rounds
+            assert need >= 1
+            for cap in sorted(c for c in {1, 127, 128, need - 1, need, need + 1} if 1 <= c <= need + 1):
+                gc.set_round_cap(cap)
+                if cap < need:
+                    with pytest.raises(gc.GColorError) as e:
+                        gpu_color(g, flags=flags)
+                    assert e.value.code == -5, (name, g.n, cap, need)
+                else:
+                    got, st2 = gpu_color(g, flags=flags)
+                    assert np.array_equal(got, ref) and st2.rounds == need, (name, g.n, cap)
+                gc.set_round_cap(0)
+    finally:
+        gc.set_round_cap(0)
+    # the library works as before after an aborted call
+    g = cases[1]
+    got, _ = gpu_color(g, flags=flags)
+    if flags == 8:
+        ref = oracle.dataflow(g.row_ptr, g.col_idx).colors
+    else:
+        ref = oracle.spec_sim(g.row_ptr, g.col_idx, None, threads=0).colors
+    assert np.array_equal(got, ref)
+
+
 # ---------------------------------------------------------------------------
 # full-size workloads
 # ---------------------------------------------------------------------------
