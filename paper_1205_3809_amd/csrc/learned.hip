@@ -723,8 +723,10 @@ hipError_t heavy_buffer(int n, int** out) {
 }
 
 int grid_for(int64_t items, int per_block) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     const int64_t want = (items + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 8));
 }
