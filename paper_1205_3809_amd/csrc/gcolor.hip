@@ -957,6 +957,61 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
     *len_out = len;
 }
 
+// inc_a_eval over the register-cached entries start, start + GS, ... < e of
+// dirty vertex w, in stages over all of them: every bitmap read, then every
+// counter atomic, then the rare flag exchanges, so that a lane keeps its
+// reads and atomics in flight together instead of waiting on each entry in
+// turn.  Entries past e hold w itself and are skipped.
+template <int GS>
+__device__ __forceinline__ void inc_a_eval_cached(const Args& a, Stage* stg, const unsigned* __restrict__ bits, int k,
+                                                  int w, int start, int e, int lim, int now, int old, const int* xs,
+                                                  const int* sv, int* cnt, bool* dlow) {
+    // which entries need their dirty bit: uncommitted preceding neighbours,
+    // and later ones (not w) holding now or old
+    unsigned need = 0u;
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) {
+        const int p = start + j * GS;
+        const int sx = sv[j];
+        const bool nd = p < e && (p < lim ? sx > 0 : (xs[j] != w && (sx == now || sx == old)));
+        need |= (nd ? 1u : 0u) << j;
+    }
+    unsigned word[kCache];
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) word[j] = (need >> j & 1u) ? bits[xs[j] >> 5] : 0u;
+    unsigned addm = 0u, subm = 0u;
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) {
+        const int p = start + j * GS;
+        if (p >= e) continue;
+        const int sx = sv[j];
+        const bool dirty = (word[j] >> (xs[j] & 31)) & 1u;
+        if (p < lim) {
+            if (sx > 0 && dirty) *dlow = true;
+            else *cnt += (sx == now);
+        } else if ((need >> j & 1u) && !dirty) {
+            if (sx == now) addm |= 1u << j;
+            else subm |= 1u << j;
+        }
+    }
+    int r[kCache];
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) {
+        r[j] = 0;
+        if (addm >> j & 1u) atomicAdd(&a.conf[xs[j]], 1);
+        else if (subm >> j & 1u) r[j] = atomicSub(&a.conf[xs[j]], 1);
+    }
+    unsigned zm = 0u;
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) zm |= ((subm >> j & 1u) && r[j] == 1 ? 1u : 0u) << j;
+    if (zm == 0u) return;
+    int f[kCache];
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) f[j] = (zm >> j & 1u) ? atomicExch(&a.cflag[xs[j]], k) : k;
+#pragma unroll
+    for (int j = 0; j < kCache; ++j) stage_append_lookup(a, stg, f[j] != k, xs[j], cset(k));
+}
+
 // Second pass over a row too long for the register cache: re-gather.
 template <int STRIDE, typename S>
 __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, const S* __restrict__ st,
@@ -1056,12 +1111,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, i
     int cnt = 0;
     bool dlow = false;
     if (cached) {
-#pragma unroll
-        for (int j = 0; j < kCache; ++j) {
-            const int p = s + lig + j * GS;
-            if (p < e && inc_a_eval(a, bits, k, w, p, lim, now, old, xs[j], sv[j], &cnt, &dlow))
-                stage_append_lookup(a, stg, true, xs[j], cs);
-        }
+        inc_a_eval_cached<GS>(a, stg, bits, k, w, s + lig, e, lim, now, old, xs, sv, &cnt, &dlow);
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
