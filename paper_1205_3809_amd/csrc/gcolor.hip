@@ -746,6 +746,62 @@ __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __rest
 }
 
 
+// inc_a_eval over N entries of dirty vertex w held in registers (ids xs,
+// words sv, at positions start, start + GS, ...; preceding below lim), in
+// stages over all of them: every bitmap read, then every counter atomic,
+// then the rare flag exchanges, so that a lane keeps its reads and atomics
+// in flight together instead of waiting on each entry in turn.  Positions
+// from e on hold w itself and are skipped.
+template <int GS, int N>
+__device__ __forceinline__ void inc_a_eval_staged(const Args& a, Stage* stg, const unsigned* __restrict__ bits, int k,
+                                                  int w, int start, int e, int lim, int now, int old, const int* xs,
+                                                  const int* sv, int* cnt, bool* dlow) {
+    // which entries need their dirty bit: uncommitted preceding neighbours,
+    // and later ones (not w) holding now or old
+    unsigned need = 0u;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int p = start + j * GS;
+        const int sx = sv[j];
+        const bool nd = p < e && (p < lim ? sx > 0 : (xs[j] != w && (sx == now || sx == old)));
+        need |= (nd ? 1u : 0u) << j;
+    }
+    unsigned word[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) word[j] = (need >> j & 1u) ? bits[xs[j] >> 5] : 0u;
+    unsigned addm = 0u, subm = 0u;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int p = start + j * GS;
+        if (p >= e) continue;
+        const int sx = sv[j];
+        const bool dirty = (word[j] >> (xs[j] & 31)) & 1u;
+        if (p < lim) {
+            if (sx > 0 && dirty) *dlow = true;
+            else *cnt += (sx == now);
+        } else if ((need >> j & 1u) && !dirty) {
+            if (sx == now) addm |= 1u << j;
+            else subm |= 1u << j;
+        }
+    }
+    int r[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        r[j] = 0;
+        if (addm >> j & 1u) atomicAdd(&a.conf[xs[j]], 1);
+        else if (subm >> j & 1u) r[j] = atomicSub(&a.conf[xs[j]], 1);
+    }
+    unsigned zm = 0u;
+#pragma unroll
+    for (int j = 0; j < N; ++j) zm |= ((subm >> j & 1u) && r[j] == 1 ? 1u : 0u) << j;
+    if (zm == 0u) return;
+    int f[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) f[j] = (zm >> j & 1u) ? atomicExch(&a.cflag[xs[j]], k) : k;
+#pragma unroll
+    for (int j = 0; j < N; ++j) stage_append_lookup(a, stg, f[j] != k, xs[j], cset(k));
+}
+
 // Heavy rows (degree > kHeavyDeg) in the wave and workgroup tiers keep an
 // active copy: the neighbours not committed yet, plus committed ones whose
 // colour lies above the bitmap range, in two segments at the row's offsets
@@ -794,7 +850,6 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
                                             int* cnt_out, bool* dlow_out, int* len_out) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
-    const int cs = cset(k);
     const HeavyView hv = heavy_view(a, w, s);
     const int len = hv.pa + hv.la;
     unsigned* F = a.hF + (size_t)hv.h * kFW;
@@ -913,13 +968,12 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) sx[j] = st[x[j]];
+        inc_a_eval_staged<GS, 4>(a, stg, bits, k, w, qb + lig, len, hv.pa, now, old, x, sx, &cnt, &dlow);
+        if (compact) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int q = qb + lig + j * GS;
-            const bool ok = q < len;
-            const bool cand = ok && inc_a_eval(a, bits, k, w, q, hv.pa, now, old, x[j], sx[j], &cnt, &dlow);
-            stage_append_lookup(a, stg, cand, x[j], cs);
-            if (compact) {
+            for (int j = 0; j < 4; ++j) {
+                const int q = qb + lig + j * GS;
+                const bool ok = q < len;
                 const bool kp = ok && hv_keep(-sx[j]);
                 const bool pre = q < hv.pa;
                 const unsigned long long m0 = __ballot(kp && pre), m1 = __ballot(kp && !pre);
@@ -955,61 +1009,6 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
     *cnt_out = cnt;
     *dlow_out = dlow;
     *len_out = len;
-}
-
-// inc_a_eval over the register-cached entries start, start + GS, ... < e of
-// dirty vertex w, in stages over all of them: every bitmap read, then every
-// counter atomic, then the rare flag exchanges, so that a lane keeps its
-// reads and atomics in flight together instead of waiting on each entry in
-// turn.  Entries past e hold w itself and are skipped.
-template <int GS>
-__device__ __forceinline__ void inc_a_eval_cached(const Args& a, Stage* stg, const unsigned* __restrict__ bits, int k,
-                                                  int w, int start, int e, int lim, int now, int old, const int* xs,
-                                                  const int* sv, int* cnt, bool* dlow) {
-    // which entries need their dirty bit: uncommitted preceding neighbours,
-    // and later ones (not w) holding now or old
-    unsigned need = 0u;
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) {
-        const int p = start + j * GS;
-        const int sx = sv[j];
-        const bool nd = p < e && (p < lim ? sx > 0 : (xs[j] != w && (sx == now || sx == old)));
-        need |= (nd ? 1u : 0u) << j;
-    }
-    unsigned word[kCache];
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) word[j] = (need >> j & 1u) ? bits[xs[j] >> 5] : 0u;
-    unsigned addm = 0u, subm = 0u;
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) {
-        const int p = start + j * GS;
-        if (p >= e) continue;
-        const int sx = sv[j];
-        const bool dirty = (word[j] >> (xs[j] & 31)) & 1u;
-        if (p < lim) {
-            if (sx > 0 && dirty) *dlow = true;
-            else *cnt += (sx == now);
-        } else if ((need >> j & 1u) && !dirty) {
-            if (sx == now) addm |= 1u << j;
-            else subm |= 1u << j;
-        }
-    }
-    int r[kCache];
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) {
-        r[j] = 0;
-        if (addm >> j & 1u) atomicAdd(&a.conf[xs[j]], 1);
-        else if (subm >> j & 1u) r[j] = atomicSub(&a.conf[xs[j]], 1);
-    }
-    unsigned zm = 0u;
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) zm |= ((subm >> j & 1u) && r[j] == 1 ? 1u : 0u) << j;
-    if (zm == 0u) return;
-    int f[kCache];
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) f[j] = (zm >> j & 1u) ? atomicExch(&a.cflag[xs[j]], k) : k;
-#pragma unroll
-    for (int j = 0; j < kCache; ++j) stage_append_lookup(a, stg, f[j] != k, xs[j], cset(k));
 }
 
 // Second pass over a row too long for the register cache: re-gather.
@@ -1050,7 +1049,6 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, i
                                              uint64_t* red, int* shc, unsigned* ffbm, int* cc, long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
-    const int cs = cset(k);
     const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
     const int old = st[w];
     if constexpr (GS == kBlock || GS == kWave) {
@@ -1111,7 +1109,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, i
     int cnt = 0;
     bool dlow = false;
     if (cached) {
-        inc_a_eval_cached<GS>(a, stg, bits, k, w, s + lig, e, lim, now, old, xs, sv, &cnt, &dlow);
+        inc_a_eval_staged<GS, kCache>(a, stg, bits, k, w, s + lig, e, lim, now, old, xs, sv, &cnt, &dlow);
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
@@ -1248,41 +1246,48 @@ __device__ __forceinline__ int inc_b_count(const int* __restrict__ row, const S*
     return c;
 }
 
-// Dirty mark from a committed vertex v (colour t) to a later row entry u
-// (word su): u is uncoloured with tentative colour t, so its tentative
-// colour must move in round k+1.  Returns true for the first mark of u.  A
-// neighbour committed in this same kernel holds a colour different from t
-// (two adjacent vertices with equal tentative colours cannot both have
-// counter 0), so reading its word before or after its commit gives no match.
-__device__ __forceinline__ bool inc_c_eval(const Args& a, unsigned* __restrict__ nbits, int k, int v, int u, int su,
-                                           int t) {
-    if (u == v || su != t) return false;
-    // round k+1's bitmap is clear when this kernel starts, so the atomic that
-    // sets the bit is the first mark (a plain read first skips most repeats)
-    const unsigned bit = 1u << (u & 31);
-    if (nbits[u >> 5] & bit) return false;
-    return !(atomicOr(&nbits[u >> 5], bit) & bit);
-}
-
+// Dirty marks from committed vertex v (colour t) over its later entries
+// start, start + STRIDE, ... < e: an entry u whose word is t is uncoloured
+// with tentative colour t, so its tentative colour must move in round k+1;
+// the first mark of u appends it to round k+1's dirty list.  A neighbour
+// committed in this same kernel holds a colour different from t (two
+// adjacent vertices with equal tentative colours cannot both have counter
+// 0), so reading its word before or after its commit gives no match.  Eight
+// entries per step, in stages (state reads, bitmap reads, then the atomics),
+// so that each stage's memory operations of a lane are in flight together.
 template <int STRIDE, typename S>
 __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__ row, Stage* stg,
                                           const S* __restrict__ st, int k, int v, int t, int start, int e) {
+    constexpr int U = 8;
     unsigned* nbits = dbits(a, k + 1);
     const int ds = dlist(k + 1);
-    for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
-        int u[4], su[4];
+    for (int p0 = start; p0 < e; p0 += U * STRIDE) {
+        int u[U], su[U];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < U; ++j) {
             const int p = p0 + j * STRIDE;
             u[j] = p < e ? row[p] : v;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) su[j] = st[u[j]];
+        for (int j = 0; j < U; ++j) su[j] = st[u[j]];
+        // round k+1's bitmap is clear when this kernel starts, so the atomic
+        // that sets a bit is its first mark; a plain read first skips most
+        // repeats
+        unsigned need = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool dirty = inc_c_eval(a, nbits, k, v, u[j], su[j], t);
-            stage_append_lookup(a, stg, dirty, u[j], ds);
-        }
+        for (int j = 0; j < U; ++j) need |= (u[j] != v && su[j] == t ? 1u : 0u) << j;
+        if (need == 0u) continue;
+        unsigned word[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) word[j] = (need >> j & 1u) ? nbits[u[j] >> 5] : ~0u;
+        unsigned setm = 0u;
+#pragma unroll
+        for (int j = 0; j < U; ++j) setm |= ((word[j] >> (u[j] & 31)) & 1u ? 0u : 1u) << j;
+        unsigned prev[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) prev[j] = (setm >> j & 1u) ? atomicOr(&nbits[u[j] >> 5], 1u << (u[j] & 31)) : ~0u;
+#pragma unroll
+        for (int j = 0; j < U; ++j) stage_append_lookup(a, stg, !((prev[j] >> (u[j] & 31)) & 1u), u[j], ds);
     }
 }
 
@@ -1477,32 +1482,44 @@ __device__ __forceinline__ void flow_store(const Args& a, int v, int c) {
 // One pass over the whole row of v, entries start, start + STRIDE, ... < e:
 // preceding entries (below lim) add their colours in 1..64 to the mask,
 // later ones are released at once -- the released vertices read v's colour
-// only in the next round, so nothing here waits for the first-fit.
+// only in the next round, so nothing here waits for the first-fit.  Four
+// entries per step, in stages: every colour byte and every release atomic
+// of the step are issued before any is used, then the rare full colours
+// (byte 255).
 template <int STRIDE>
 __device__ __forceinline__ uint64_t flow_row(const Args& a, Stage* stg, const uint8_t* __restrict__ cb, int v,
                                              int start, int lim, int e, int set) {
     uint64_t m = 0;
     for (int p0 = start; p0 < e; p0 += 4 * STRIDE) {
         int x[4];
-        bool r[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int p = p0 + j * STRIDE;
             x[j] = p < e ? a.colp[p] : v;
         }
+        unsigned pre = 0u, rel = 0u;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int p = p0 + j * STRIDE;
-            r[j] = false;
-            if (p < lim) {
-                const unsigned c = (unsigned)(flow_colour(cb, a.color, x[j]) - 1);
-                if (c < 64u) m |= 1ull << c;
-            } else if (x[j] != v) {
-                r[j] = atomicSub(&a.conf[x[j]], 1) == 1;
-            }
+            pre |= (p < lim ? 1u : 0u) << j;
+            rel |= (p >= lim && x[j] != v ? 1u : 0u) << j;
+        }
+        int c[4], left[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c[j] = (pre >> j & 1u) ? (int)cb[x[j]] : 0;
+            left[j] = (rel >> j & 1u) ? atomicSub(&a.conf[x[j]], 1) : 0;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) stage_append_lookup(a, stg, r[j], x[j], set);
+        for (int j = 0; j < 4; ++j)
+            if (c[j] == 255) c[j] = a.color[x[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned b = (unsigned)(c[j] - 1);
+            if (b < 64u) m |= 1ull << b;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) stage_append_lookup(a, stg, left[j] == 1, x[j], set);
     }
     return m;
 }
