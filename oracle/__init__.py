@@ -9,10 +9,13 @@ Two layers:
 * ``oracle.c`` (loaded through ctypes): serial greedy first-fit (Algorithm 1),
   the round-synchronous simulation of the iterative speculative colouring
   (Algorithm 2, snapshot reads, losers revoked), the dataflow colouring
-  (Algorithm 3) read in rounds, and smallest-last ordering.  Fast enough for
-  full-size graphs.
+  (Algorithm 3) read in rounds, the block Gauss-Seidel variant of
+  Algorithm 2 (fixed id blocks coloured in order, seeing their own colours
+  of the round), and smallest-last ordering.  Fast enough for full-size
+  graphs.
 * Pure-Python definitions below (``greedy_py``, ``spec_sim_py``,
-  ``dataflow_py``) for small inputs, written straight from the set notation,
+  ``block_gs_py``, ``dataflow_py``) for small inputs, written straight from
+  the set notation,
   plus brute-force tools (chromatic number, greedy over every ordering, the
   longest chain of preceding vertices) used to pin the oracle.
 
@@ -62,6 +65,9 @@ def _load():
     lib.or_smallest_last.restype = ctypes.c_int32
     lib.or_dataflow.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, i32p]
     lib.or_dataflow.restype = ctypes.c_int32
+    lib.or_block_gs.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, i32p, i64p,
+                                ctypes.c_int32, ctypes.c_int32]
+    lib.or_block_gs.restype = ctypes.c_int32
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -145,6 +151,37 @@ def dataflow(row_ptr, col_idx, key: Optional[np.ndarray] = None) -> DataflowResu
     return DataflowResult(color[:n], int(k), rnd[:n])
 
 
+class BlockResult(NamedTuple):
+    colors: np.ndarray  # int32[n]
+    rounds: int
+    log: np.ndarray     # int64[rounds, 4]: (k, |U_k|, sum deg over U_k, losers)
+
+
+def block_gs(row_ptr, col_idx, key: Optional[np.ndarray] = None, block: int = 64,
+             max_rounds: Optional[int] = None) -> BlockResult:
+    """Block Gauss-Seidel speculative colouring: Algorithm 2 in rounds where
+    each block of `block` consecutive ids colours its worklist vertices in id
+    order, seeing the block's own colours of the round; conflicts by (key,
+    id) precedence as in Algorithm 2."""
+    row_ptr, col_idx = _csr_args(row_ptr, col_idx)
+    n = row_ptr.shape[0] - 1
+    if key is not None:
+        key = np.ascontiguousarray(key, dtype=np.uint32)
+    if max_rounds is None:
+        max_rounds = max(n, 1)
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    max_log = max(1, min(max_rounds, 1 << 20))
+    log = np.zeros((max_log, 4), dtype=np.int64)
+    k = _load().or_block_gs(n, _p(row_ptr, ctypes.c_int32), _p(col_idx, ctypes.c_int32),
+                            _p(key, ctypes.c_uint32), int(block), _p(color, ctypes.c_int32),
+                            _p(log, ctypes.c_int64), max_log, max_rounds)
+    if k == -1:
+        raise ValueError("block size must be at least 1")
+    if k < 0:
+        raise RuntimeError("block_gs: round cap %d exceeded" % max_rounds)
+    return BlockResult(color[:n], int(k), log[:k].copy())
+
+
 def smallest_last_rank(row_ptr, col_idx) -> Tuple[np.ndarray, int]:
     """Matula-Beck smallest-last order: rank[v] = position in the colouring
     order (0 first).  Returns (rank, degeneracy)."""
@@ -209,6 +246,33 @@ def spec_sim_py(adj: List[List[int]], key=None, trace=None) -> Tuple[List[int], 
             trace(k, list(U), dict(tent), list(R), list(color))
         U = R
     return color, k, log
+
+
+def block_gs_py(adj: List[List[int]], key=None, block: int = 1) -> Tuple[List[int], int]:
+    """The block Gauss-Seidel rounds from their set definition: in each
+    round, block b = {v : v // block == b} takes its uncoloured vertices in
+    id order, each choosing the smallest colour held neither by a coloured
+    neighbour nor by a neighbour of the same block chosen earlier in the
+    round; then every uncoloured vertex whose choice equals that of a
+    preceding ((key, id) order) uncoloured neighbour gives it back.
+    Returns (colours, rounds)."""
+    n = len(adj)
+    color = [0] * n
+    k = 0
+    while any(c == 0 for c in color):
+        k += 1
+        U = [v for v in range(n) if color[v] == 0]
+        chosen = {}
+        for v in U:  # ascending id: within a block, earlier choices are known
+            seen = {color[w] for w in adj[v] if color[w] > 0}
+            seen |= {chosen[w] for w in adj[v] if w in chosen and w // block == v // block}
+            chosen[v] = first_fit(seen)
+        keep = [v for v in U
+                if not any(w in chosen and chosen[w] == chosen[v] and _order_key(key, w) < _order_key(key, v)
+                           for w in adj[v] if w != v)]
+        for v in keep:
+            color[v] = chosen[v]
+    return color, k
 
 
 def dataflow_py(adj: List[List[int]], key=None) -> Tuple[List[int], int, List[int]]:

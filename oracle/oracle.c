@@ -306,3 +306,97 @@ int32_t or_dataflow(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, c
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/*
+ * Block Gauss-Seidel variant of the speculative colouring (Algorithm 2 with
+ * the static schedule of section "Scalability Results": each thread owns a
+ * fixed contiguous range of vertices and visits it in index order, seeing its
+ * own colours of the current round at once).  Blocks are the id ranges
+ * [b*B, (b+1)*B).  Round k, with U the uncoloured vertices:
+ *   S = copy(color)
+ *   phase 1, for each block, for v in U in the block in ascending id:
+ *     tent[v] = min{c >= 1 : c not in {S[w] : w in adj(v)}
+ *                                  and not in {tent[w] : w in adj(v), w in U,
+ *                                              w in v's block, w < v}}
+ *   phase 2, for v in U: v loses if some neighbour w holds its colour
+ *     (tent[w] for w in U, S[w] otherwise) and (key[w], w) < (key[v], v)
+ *   winners keep tent[v]; losers stay uncoloured (next worklist).
+ * B = 1 is the round-synchronous simulation above; B >= n (one block) is the
+ * serial greedy in index order, finished in one round.  The blocks are
+ * independent within phase 1, so their order of visit does not matter.
+ * log (may be NULL) receives per round: k, |U_k|, sum of degrees over U_k,
+ * number of losers; at most max_log rounds.
+ * Returns the number of rounds, or -5 when max_rounds is exceeded.
+ */
+int32_t or_block_gs(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* key,
+                    int32_t block, int32_t* color, int64_t* log, int32_t max_log, int32_t max_rounds) {
+    if (block < 1) return -1;
+    const int32_t dmax = or_max_degree(n, row_ptr);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t* S = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int32_t* tent = (int32_t*)malloc(sizeof(int32_t) * nn);
+    unsigned char* inU = (unsigned char*)malloc(nn);
+    unsigned char* lose = (unsigned char*)malloc(nn);
+    int64_t* forbidden = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax + 2));
+    for (int32_t c = 0; c < dmax + 2; ++c) forbidden[c] = -1;
+    for (int32_t v = 0; v < n; ++v) color[v] = 0;
+    int64_t nU = n;
+    int32_t k = 0;
+    while (nU > 0) {
+        if (k >= max_rounds) { k = -5; break; }
+        ++k;
+        memcpy(S, color, sizeof(int32_t) * (size_t)n);
+        for (int32_t v = 0; v < n; ++v) inU[v] = color[v] == 0;
+
+        /* Phase 1: blocks in turn, each block's worklist vertices in id order. */
+        for (int64_t b0 = 0; b0 < n; b0 += block) {
+            const int64_t b1 = b0 + block < n ? b0 + block : n;
+            for (int64_t vv = b0; vv < b1; ++vv) {
+                const int32_t v = (int32_t)vv;
+                if (!inU[v]) continue;
+                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                    const int32_t w = col_idx[e];
+                    if (w == v) continue;
+                    forbidden[S[w]] = v;
+                    if (inU[w] && w >= b0 && w < v) forbidden[tent[w]] = v;
+                }
+                int32_t c = 1;
+                while (forbidden[c] == v) ++c;
+                tent[v] = c;
+            }
+        }
+
+        /* Phase 2: conflicts against every neighbour's colour of this round. */
+        int64_t work = 0, nR = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!inU[v]) continue;
+            unsigned char l = 0;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t w = col_idx[e];
+                if (w == v) continue;
+                const int32_t cw = inU[w] ? tent[w] : S[w];
+                if (cw == tent[v] && or_before(key, w, v)) l = 1;
+            }
+            lose[v] = l;
+            work += row_ptr[v + 1] - row_ptr[v];
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            if (!inU[v]) continue;
+            if (lose[v]) ++nR;
+            else color[v] = tent[v];
+        }
+        if (log && k <= max_log) {
+            log[4 * (k - 1) + 0] = k;
+            log[4 * (k - 1) + 1] = nU;
+            log[4 * (k - 1) + 2] = work;
+            log[4 * (k - 1) + 3] = nR;
+        }
+        nU = nR;
+    }
+    free(S);
+    free(tent);
+    free(inU);
+    free(lose);
+    free(forbidden);
+    return k;
+}
