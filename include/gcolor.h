@@ -177,6 +177,38 @@ int gcolor_set_round_cap(int32_t max_rounds);
 int gcolor_get_round_cap(int32_t* max_rounds);
 
 /*
+ * Block Gauss-Seidel variant of the speculative colouring (Algorithm 2 run
+ * with the static schedule of the section "Scalability Results": a thread
+ * owns a fixed contiguous range of vertices, visits it in index order and
+ * sees its own colours of the round at once).  A different colouring from
+ * color_graph's, deterministic for a given block_size:
+ *   blocks are the id ranges [b*block_size, (b+1)*block_size); in each round
+ *   every block gives its uncoloured vertices, in ascending id, the smallest
+ *   colour held neither by a coloured neighbour nor by a neighbour of the
+ *   same block chosen earlier in the round; then an uncoloured vertex whose
+ *   choice equals that of a neighbour preceding it in (priority, id) order
+ *   gives its choice back, and the others keep theirs.
+ * block_size 1 gives exactly color_graph's colouring; one block holding every
+ * vertex gives the serial greedy in index order in one round.
+ *   n, row_ptr, col_idx, priority, colors_out, stream: as color_graph (rows
+ *                 need not be sorted; priority may be NULL);
+ *   block_size    1 .. 2048;
+ *   workspace     device memory of gcolor_blocks_workspace_bytes(n) bytes, or
+ *                 NULL for the library's cached per-device allocation;
+ *   stats         optional (host): rounds, largest colour, and the sum over
+ *                 rounds of the degrees of the uncoloured vertices.
+ * The CSR is not validated.  The process-wide round cap of
+ * gcolor_set_round_cap applies.  Errors: GCOLOR_EINVAL (negative n,
+ * block_size outside 1..2048, NULL arrays), GCOLOR_EWORKSPACE,
+ * GCOLOR_EHIP, GCOLOR_EROUNDS.  Blocking: returns after the colouring is
+ * complete on `stream`.
+ */
+size_t gcolor_blocks_workspace_bytes(int32_t n);
+int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* priority,
+                       int32_t block_size, int32_t* colors_out, void* workspace, size_t ws_bytes,
+                       gcolor_stats_t* stats, gcolor_stream_t stream);
+
+/*
  * Batch tuning (process-wide, applies to later color_graph_batch calls).
  * block_threads: threads per workgroup, 256 or 1024, or 0 for the default
  * (1024 when the LDS capacity below is at least 16384 vertices, else 256).

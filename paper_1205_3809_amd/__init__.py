@@ -8,7 +8,9 @@ binding raises.
 from ._binding import (  # noqa: F401
     GColorError,
     Stats,
+    blocks_workspace_bytes,
     color_graph,
+    color_graph_blocks,
     color_graph_ex,
     library_path,
     strerror,

@@ -77,6 +77,11 @@ def _load():
     lib.gcolor_set_kernel_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.gcolor_set_kernel_blocks.restype = ctypes.c_int
     lib.gcolor_get_kernel_blocks.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
+    lib.gcolor_blocks_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.gcolor_blocks_workspace_bytes.restype = ctypes.c_size_t
+    lib.color_graph_blocks.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
+                                       ctypes.POINTER(_Stats), vp]
+    lib.color_graph_blocks.restype = ctypes.c_int
     lib.gcolor_set_round_cap.argtypes = [ctypes.c_int32]
     lib.gcolor_set_round_cap.restype = ctypes.c_int
     lib.gcolor_get_round_cap.argtypes = [ctypes.POINTER(ctypes.c_int32)]
@@ -197,6 +202,38 @@ def color_graph_ex(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optio
             detail.append((int(logbuf[i].committed), int(logbuf[i].dirty), int(logbuf[i].dirty_edges),
                            int(logbuf[i].scanned)))
     return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), log, detail)
+
+
+def blocks_workspace_bytes(n: int) -> int:
+    return int(_lib.gcolor_blocks_workspace_bytes(int(n)))
+
+
+def color_graph_blocks(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional[torch.Tensor] = None,
+                       block_size: int = 64, colors_out: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None, stream=None):
+    """Block Gauss-Seidel colouring (fixed id blocks of block_size vertices
+    coloured in order within each round).  Returns (colors, Stats); the
+    Stats carry no per-round log."""
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must have n+1 entries")
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    pr = _dev_ptr(priority, "priority", _KEY, n)
+    if colors_out is None:
+        colors_out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    co = _dev_ptr(colors_out, "colors_out", _I32, n)
+    ws, ws_bytes = None, 0
+    if workspace is not None:
+        ws = _dev_ptr(workspace, "workspace", (torch.uint8, torch.int8, torch.int32, torch.int64))
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = _Stats()
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.color_graph_blocks(n, rp, ci, pr, int(block_size), co, ws, ws_bytes, ctypes.byref(st),
+                                     _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "color_graph_blocks")
+    return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), [], [])
 
 
 def color_graph(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional[torch.Tensor] = None,

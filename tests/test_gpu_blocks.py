@@ -1,0 +1,137 @@
+"""Block Gauss-Seidel colouring (color_graph_blocks) vs the CPU oracle,
+through the C ABI: every colour, the round count, the largest colour and the
+edge work (sum over rounds of the degrees of the uncoloured vertices) equal
+the oracle's on the same seeded inputs; block size 1 equals color_graph's
+colouring and one block equals the serial greedy in one round.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def gpu_blocks(g, key=None, block=64, workspace=None):
+    import paper_1205_3809_amd as gc
+    pr = None if key is None else dev(np.ascontiguousarray(key, dtype=np.uint32).view(np.int32))
+    col, st = gc.color_graph_blocks(dev(g.row_ptr), dev(g.col_idx), pr, block_size=block, workspace=workspace)
+    torch.cuda.synchronize()
+    return col.cpu().numpy(), st
+
+
+def check(g, key=None, block=64, label=""):
+    print("case %s n=%d nnz=%d block=%d key=%s" % (label, g.n, g.nnz, block, key is not None), flush=True)
+    ref = oracle.block_gs(g.row_ptr, g.col_idx, key, block)
+    col, st = gpu_blocks(g, key, block)
+    mism = np.flatnonzero(col != ref.colors)
+    assert mism.size == 0, "%s: %d mismatches, first at %s" % (label, mism.size, mism[:5])
+    assert st.rounds == ref.rounds
+    assert st.num_colors == (int(ref.colors.max()) if g.n else 0)
+    assert st.edge_work == int(ref.log[:, 2].sum())
+    return col, st
+
+
+@pytest.mark.parametrize("block", [1, 2, 7, 64, 1000, 2048])
+@pytest.mark.parametrize("order", ["natural", "perm", "ties"])
+def test_rmat_blocks(block, order):
+    g = graphgen.rmat(14, 8, (0.55, 0.1, 0.1), 3)
+    key = {"natural": None, "perm": graphgen.random_priority(g.n, 8),
+           "ties": graphgen.random_keys(g.n, 9, bits=4)}[order]
+    check(g, key, block, "rmat14-" + order)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 65, 1000])
+@pytest.mark.parametrize("block", [1, 3, 4, 64])
+def test_paths_and_empty(n, block):
+    check(graphgen.path(n), None, block, "path")
+    check(graphgen.empty(n), None, block, "empty")
+
+
+@pytest.mark.parametrize("block", [1, 16, 333])
+def test_structured(block):
+    check(graphgen.complete(150), None, block, "complete")
+    check(graphgen.star(3000, 0), None, block, "star-first")
+    check(graphgen.star(3000, 2999), None, block, "star-last")
+    check(graphgen.grid((64, 64)), None, block, "grid5")
+    check(graphgen.grid((30, 31), True), graphgen.random_priority(930, 2), block, "grid9-perm")
+    check(graphgen.rgg(20000, 12.0, 4), None, block, "rgg")
+
+
+def test_block_one_is_color_graph():
+    import paper_1205_3809_amd as gc
+    g = graphgen.rmat(15, 8, (0.55, 0.1, 0.1), 5)
+    for key in (None, graphgen.random_priority(g.n, 4)):
+        col, st = gpu_blocks(g, key, 1)
+        pr = None if key is None else dev(np.ascontiguousarray(key, dtype=np.uint32).view(np.int32))
+        ref, rst = gc.color_graph_ex(dev(g.row_ptr), dev(g.col_idx), pr, stats=True)
+        assert np.array_equal(col, ref.cpu().numpy()) and st.rounds == rst.rounds
+
+
+def test_one_block_is_the_serial_greedy():
+    g = graphgen.rmat(11, 8, (0.55, 0.1, 0.1), 7)
+    assert g.n <= 2048
+    for key in (None, graphgen.random_priority(g.n, 5)):
+        col, st = gpu_blocks(g, key, 2048)
+        assert st.rounds == 1
+        assert np.array_equal(col, oracle.greedy(g.row_ptr, g.col_idx, None))
+
+
+def test_unsorted_rows_loops_and_repeats():
+    g = graphgen.rmat(12, 8, (0.55, 0.1, 0.1), 6)
+    rng = np.random.default_rng(1)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    dst = g.col_idx.astype(np.int64)
+    up = np.flatnonzero(src < dst)
+    rep = rng.choice(up, up.size // 5, replace=False)
+    loops = rng.choice(g.n, g.n // 10, replace=False)
+    s2 = np.concatenate([src, src[rep], dst[rep], loops])
+    d2 = np.concatenate([dst, dst[rep], src[rep], loops])
+    order = np.lexsort((rng.random(s2.size), s2))  # rows grouped, entries shuffled
+    s2, d2 = s2[order], d2[order]
+    rp = np.zeros(g.n + 1, np.int64)
+    np.add.at(rp, s2 + 1, 1)
+    h = graphgen.CSR(g.n, np.cumsum(rp).astype(np.int32), d2.astype(np.int32))
+    for block in (1, 5, 64):
+        col, _ = gpu_blocks(h, None, block)
+        assert np.array_equal(col, oracle.block_gs(g.row_ptr, g.col_idx, None, block).colors)
+
+
+def test_errors_workspace_and_round_cap():
+    import paper_1205_3809_amd as gc
+    g = graphgen.rmat(12, 8, (0.55, 0.1, 0.1), 8)
+    for bad in (0, -3, 2049):
+        with pytest.raises(gc.GColorError) as e:
+            gpu_blocks(g, None, bad)
+        assert e.value.code == -1
+    ws = torch.empty(gc.blocks_workspace_bytes(g.n), dtype=torch.uint8, device="cuda")
+    ref = oracle.block_gs(g.row_ptr, g.col_idx, None, 16)
+    for w in (ws, ws, None):
+        col, st = gpu_blocks(g, None, 16, workspace=w)
+        assert np.array_equal(col, ref.colors)
+    with pytest.raises(gc.GColorError) as e:
+        gpu_blocks(g, None, 16, workspace=ws[:1000])
+    assert e.value.code == -3
+    assert ref.rounds >= 2
+    try:
+        gc.set_round_cap(ref.rounds - 1)
+        with pytest.raises(gc.GColorError) as e:
+            gpu_blocks(g, None, 16)
+        assert e.value.code == -5
+        gc.set_round_cap(ref.rounds)
+        col, st = gpu_blocks(g, None, 16)
+        assert np.array_equal(col, ref.colors) and st.rounds == ref.rounds
+    finally:
+        gc.set_round_cap(0)
+
+
+@pytest.mark.parametrize("block", [64, 1024])
+def test_rmat_scale20(block):
+    """R-MAT scale 20, edge factor 8, (0.55, 0.1, 0.1, 0.25), natural order."""
+    check(graphgen.rmat(20, 8, (0.55, 0.1, 0.1), 11), None, block, "rmat20")
