@@ -173,6 +173,77 @@ def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings, out_
     return out
 
 
+def bench_blocks(args):
+    """The block Gauss-Seidel variant (color_graph_blocks) on a single-graph
+    workload: K timed colourings; the roofline is priced over the whole call
+    (the entry point records no per-kernel events)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1205_3809_amd as gc
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+    g = make_graph(args.workload)
+    key = graphgen.random_priority(g.n, 12) if args.order == "perm" else None
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    pr = None if key is None else torch.from_numpy(key.view(np.int32)).to(dev)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ws = torch.empty(gc.blocks_workspace_bytes(g.n), dtype=torch.uint8, device=dev)
+    B = args.block_size
+    _, st = gc.color_graph_blocks(rp, ci, pr, block_size=B, colors_out=out, workspace=ws)
+    torch.cuda.synchronize()
+    log("blocks B=%d: rounds=%d colours=%d edge_work=%.2f x nnz" % (B, st.rounds, st.num_colors,
+                                                                   st.edge_work / max(g.nnz, 1)))
+
+    def step():
+        gc.color_graph_blocks(rp, ci, pr, block_size=B, colors_out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_per_step = 1000.0 * wall / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    log("timed %d steps: %.3f ms/step (wall), %.3f ms/step (events)" % (args.steps, ms_per_step, ev_ms))
+    # algorithmic bytes of one colouring: per round, both row passes read
+    # neighbour id + colour (8 B) per entry of an uncoloured row and the
+    # three kernels 24 B per uncoloured vertex (row_ptr pair, colour, choice,
+    # verdict), plus the per-round scan of every colour and the final write
+    algo = 16 * st.edge_work + 24 * g.n * st.rounds + 4 * g.n
+    achieved = algo / (ev_ms / 1e3) / 1e9
+    roofline = {"kernel": "whole call (k_blk_first + k_blk_check + k_blk_commit)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_step": int(algo)}
+    p = WORKLOADS[args.workload][1]
+    config = {"workload": "%s-%s" % (args.workload, args.order), "engine": "blocks", "block_size": B,
+              "n": g.n, "nnz": g.nnz, "edges": g.edges}
+    config.update({k: v for k, v in p.items()})
+    res = {
+        "metric": "edges colored/sec + % HBM peak at R-MAT s24; colors vs serial greedy",
+        "value": round(g.edges / (ms_per_step / 1e3), 1), "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic", "config": config, "colors": int(st.num_colors), "rounds": int(st.rounds),
+        "edge_work_over_nnz": round(st.edge_work / max(g.nnz, 1), 3), "parity_vs_oracle": None,
+        "roofline": roofline, "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--derive-traffic":
         # --derive-traffic FETCH_CSV WRITE_CSV WORKLOAD ORDER
@@ -186,9 +257,10 @@ def main():
     ap.add_argument("--order", default="natural", choices=["natural", "perm"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event-timed pass")
-    ap.add_argument("--engine", default="incremental", choices=["incremental", "plain", "dataflow"],
+    ap.add_argument("--engine", default="incremental", choices=["incremental", "plain", "dataflow", "blocks"],
                     help="dataflow: the dataflow algorithm in rounds (a different colouring: the serial "
-                         "greedy's)")
+                         "greedy's); blocks: the block Gauss-Seidel variant (a different colouring)")
+    ap.add_argument("--block-size", type=int, default=64, help="vertices per block of --engine blocks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--autotune", action="store_true",
@@ -201,6 +273,8 @@ def main():
         return bench_batch(args)
     if WORKLOADS[args.workload][0] == "learned" and args.gpus == 1:
         return bench_learned(args)
+    if args.engine == "blocks" and args.gpus == 1:
+        return bench_blocks(args)
     if args.gpus != 1:
         print("bench.py: the colouring runs on one GPU (got --gpus %d); sharding the method across "
               "GPUs is not built." % args.gpus,

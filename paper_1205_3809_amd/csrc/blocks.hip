@@ -7,8 +7,8 @@
 //   phase 1 (k_blk_first, one wavefront per block): the block's vertices of
 //     U in ascending id take the smallest colour held neither by a coloured
 //     neighbour nor by a neighbour of the same block chosen earlier in this
-//     round (kept in LDS while the block is coloured, then copied to tent);
-//   phase 2 (k_blk_check, one thread per vertex): v in U loses when a
+//     round (kept in LDS while the block is coloured, and written to tent);
+//   phase 2 (k_blk_check, one wavefront per 64 vertices): v in U loses when a
 //     neighbour holds its colour (tent for vertices of U, the committed
 //     colour otherwise) and precedes it in (key, id) order;
 //   phase 3 (k_blk_commit): winners commit, losers form U for round k+1.
@@ -21,7 +21,13 @@
 // Memory: colors_out holds the committed colours (0 = uncoloured); the
 // workspace holds a 256-byte control block, tent (int32[n]) and the phase-2
 // verdicts (int32[n]).  Block sizes run from 1 to kMaxBlock (LDS per
-// wavefront: 4 bytes per vertex of its block).
+// wavefront of phase 1: 4 bytes per vertex of its block plus the state of
+// one 64-vertex chunk).
+//
+// Both row passes work on chunks of 64 consecutive vertices: a wavefront
+// compacts the chunk's vertices of U, prefix-sums their degrees and walks
+// their rows as one concatenated range, 64 entries per step, so a hub row is
+// spread over every lane and light rows share a step.
 
 #include <hip/hip_runtime.h>
 
@@ -95,45 +101,206 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Phase 1: one wavefront per block, its uncoloured vertices in ascending id;
-// the lanes stride each row (four entries per lane per step) and OR their
-// masks of the colours base..base+63 they see.
+// Per-wavefront LDS for a chunk of 64 consecutive vertices.  For the k-th
+// uncoloured vertex of the chunk (ascending id): its row start, its position
+// in the chunk, the sum of the degrees of the uncoloured vertices before it
+// (pre[nU] = the chunk's total) and, in phase 2, its tentative colour.  m and
+// d collect per vertex what the chunk's row walk finds.
+struct ChunkLds {
+    unsigned long long m[64];  // phase 1: colours 1..64 taken; phase 2: nonzero = loses
+    unsigned long long d[64];  // phase 1: uncoloured earlier vertices of the chunk adjacent
+    int pre[65];
+    int rs[64];
+    int qp[64];
+    int tv[64];
+    int pad[3];
+};
+static_assert(sizeof(ChunkLds) % 8 == 0, "chunk LDS alignment");
+
+// LDS of one wavefront of k_blk_first: its chunk state, then one int per
+// vertex of its block.
+__host__ __device__ constexpr size_t blk_wave_lds(int B) {
+    return sizeof(ChunkLds) + (((size_t)B * sizeof(int) + 7) & ~(size_t)7);
+}
+
+// Sets up the chunk [c0, c1): returns the mask of its uncoloured vertices
+// (bit q = vertex c0 + q); for them fills pre/rs/qp (and tv from tent when
+// tent is given) and clears m and d.  total = the sum of their degrees, k =
+// the calling lane's rank among them.  Uniform over the wavefront.
+__device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ color, const int* __restrict__ tent,
+                                                ChunkLds* L, int lane, int& total, int& k) {
+    const int u = c0 + lane;
+    int s = 0, e = 0;
+    bool unc = false;
+    if (u < c1) {
+        s = row_ptr[u];
+        e = row_ptr[u + 1];
+        unc = color[u] == 0;
+    }
+    const uint64_t mask = __ballot(unc);
+    if (mask == 0) return 0;
+    const int deg = unc ? e - s : 0;
+    int x = deg;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63);
+    k = __popcll(mask & ((1ull << lane) - 1));
+    if (unc) {
+        L->pre[k] = x - deg;
+        L->rs[k] = s;
+        L->qp[k] = lane;
+        L->m[k] = 0;
+        L->d[k] = 0;
+        if (tent) L->tv[k] = tent[u];
+    }
+    if (lane == 0) L->pre[__popcll(mask)] = total;
+    wave_sync();
+    return mask;
+}
+
+// The uncoloured vertex of the chunk whose row holds entry j of the
+// concatenated rows: the largest k < nU with pre[k] <= j.
+__device__ __forceinline__ int chunk_owner(const ChunkLds* L, int nU, int j) {
+    int lo = 0, hi = nU;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L->pre[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Entries i0 .. i0+3 of the chunk's concatenated rows: their owners (-1 past
+// the end) and column ids.  One search, then the owner only moves forward.
+__device__ __forceinline__ void chunk_entries(const ChunkLds* L, int nU, int total, int i0,
+                                              const int* __restrict__ col_idx, int (&o)[4], int (&w)[4]) {
+    int oc = i0 < total ? chunk_owner(L, nU, i0) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int idx = i0 + j;
+        o[j] = -1;
+        w[j] = 0;
+        if (idx < total) {
+            while (L->pre[oc + 1] <= idx) ++oc;  // pre[nU] = total > idx bounds the walk
+            o[j] = oc;
+            w[j] = col_idx[L->rs[oc] + (idx - L->pre[oc])];
+        }
+    }
+}
+
+// First fit for vertex v from colour `base` on, the whole wavefront striding
+// its row (four entries per lane per step) and OR-ing masks of the colours
+// base..base+63 it sees.  lt must hold the choices of every uncoloured vertex
+// of the block before v.
+__device__ int blk_first_fit(int v, int v0, int base, const int* __restrict__ row_ptr,
+                             const int* __restrict__ col_idx, const int* __restrict__ color, const int* lt,
+                             int lane) {
+    const int s = row_ptr[v], e = row_ptr[v + 1];
+    for (;; base += 64) {
+        uint64_t m = 0;
+        for (int p0 = s + lane; p0 < e; p0 += 4 * 64) {
+            int w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = p0 + j * 64 < e ? col_idx[p0 + j * 64] : v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const unsigned c = (unsigned)(blk_seen(color, lt, w[j], v, v0) - base);
+                if (c < 64u) m |= 1ull << c;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o);
+        if (~m) return base + __builtin_ctzll(~m);
+    }
+}
+
+// Phase 1: one wavefront per block, in chunks of 64 vertices.  The lanes walk
+// the concatenated rows of the chunk's uncoloured vertices and record, per
+// vertex, the colours 1..64 that coloured neighbours and uncoloured
+// neighbours of earlier chunks of the block hold (the latter from LDS), and
+// which earlier uncoloured vertices of the chunk are adjacent.  Then the
+// chunk's vertices are settled in ascending id: each takes the first colour
+// free of both; a vertex with all of 1..64 taken is settled by a full
+// first-fit scan of its row (blk_first_fit).
 __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long nblocks,
                                                         const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
                                                         const int* __restrict__ color, int* __restrict__ tent) {
-    extern __shared__ int lds[];
+    extern __shared__ unsigned long long lds64[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int* lt = lds + wid * B;
+    char* wbase = reinterpret_cast<char*>(lds64) + (size_t)wid * blk_wave_lds(B);
+    ChunkLds* L = reinterpret_cast<ChunkLds*>(wbase);
+    int* lt = reinterpret_cast<int*>(wbase + sizeof(ChunkLds));
     for (long long b = (long long)blockIdx.x * kWaves + wid; b < nblocks; b += (long long)gridDim.x * kWaves) {
         const int v0 = (int)(b * B);
         const int v1 = (int)std::min<long long>(n, (long long)v0 + B);
-        for (int v = v0; v < v1; ++v) {
-            if (color[v] != 0) continue;  // uniform over the wavefront
-            const int s = row_ptr[v], e = row_ptr[v + 1];
-            int t = 0;
-            for (int base = 1; t == 0; base += 64) {
-                uint64_t m = 0;
-                for (int p0 = s + lane; p0 < e; p0 += 4 * 64) {
-                    int w[4];
+        for (int c0 = v0; c0 < v1; c0 += 64) {
+            const int c1 = std::min(v1, c0 + 64);
+            int total = 0, k = 0;
+            const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, L, lane, total, k);
+            if (mask == 0) continue;  // uniform
+            const int nU = __popcll(mask);
+            int acck = -1;
+            uint64_t am = 0, ad = 0;
+            for (int jb = 0; jb < total; jb += 4 * 64) {
+                int o[4], w[4], c[4];
+                chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) w[j] = p0 + j * 64 < e ? col_idx[p0 + j * 64] : v;
+                for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? color[w[j]] : 0;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const unsigned c = (unsigned)(blk_seen(color, lt, w[j], v, v0) - base);
-                        if (c < 64u) m |= 1ull << c;
+                for (int j = 0; j < 4; ++j) {
+                    if (o[j] < 0) continue;
+                    if (o[j] != acck) {
+                        if (acck >= 0) {
+                            if (am) atomicOr(&L->m[acck], am);
+                            if (ad) atomicOr(&L->d[acck], ad);
+                        }
+                        am = ad = 0;
+                        acck = o[j];
                     }
+                    const int v = c0 + L->qp[o[j]];
+                    if (w[j] == v) continue;
+                    int cc = c[j];
+                    if (cc == 0) {
+                        if (w[j] >= v0 && w[j] < c0) {
+                            cc = lt[w[j] - v0];
+                        } else if (w[j] >= c0 && w[j] < v) {
+                            ad |= 1ull << (w[j] - c0);
+                            continue;
+                        }
+                    }
+                    if ((unsigned)(cc - 1) < 64u) am |= 1ull << (cc - 1);
                 }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o);
-                if (~m) t = base + __builtin_ctzll(~m);
             }
-            if (lane == 0) lt[v - v0] = t;
+            if (acck >= 0) {
+                if (am) atomicOr(&L->m[acck], am);
+                if (ad) atomicOr(&L->d[acck], ad);
+            }
             wave_sync();
+            const bool unc = (mask >> lane) & 1;
+            uint64_t F = unc ? L->m[k] : 0, dep = unc ? L->d[k] : 0;
+            int t = 0;
+            for (uint64_t rem = mask; rem; rem &= rem - 1) {
+                const int q = __builtin_ctzll(rem);
+                int tq = __shfl(~F ? __builtin_ctzll(~F) + 1 : 0, q);
+                if (tq == 0) {  // colours 1..64 all taken around vertex c0 + q
+                    if (unc && lane < q) lt[c0 - v0 + lane] = t;
+                    wave_sync();
+                    tq = blk_first_fit(c0 + q, v0, 65, row_ptr, col_idx, color, lt, lane);
+                }
+                if (lane == q) t = tq;
+                if (((dep >> q) & 1) && tq <= 64) F |= 1ull << (tq - 1);
+            }
+            if (unc) {
+                lt[c0 - v0 + lane] = t;
+                tent[c0 + lane] = t;
+            }
+            wave_sync();  // the chunk state and lt are read by the next chunk
         }
-        for (int i = lane; i < v1 - v0; i += 64)
-            if (color[v0 + i] == 0) tent[v0 + i] = lt[i];
-        wave_sync();  // the slot is reused by the wavefront's next block
     }
 }
 
@@ -148,32 +315,54 @@ __device__ __forceinline__ long long blk_block_sum(long long x, long long* red) 
     return t;  // valid in thread 0
 }
 
-// Phase 2: verdict of every uncoloured vertex against this round's colours.
+// Phase 2: verdict of every uncoloured vertex against this round's colours,
+// one wavefront per chunk of 64 vertices walking the concatenated rows of
+// its uncoloured vertices.  tent holds every vertex's current colour: phase
+// 1 writes it for the uncoloured vertices only, and a vertex commits the
+// value it holds there, so one gather serves both kinds of neighbour.
 __global__ __launch_bounds__(kThreads) void k_blk_check(int n, const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
                                                         const uint32_t* __restrict__ key,
                                                         const int* __restrict__ color,
                                                         const int* __restrict__ tent, int* __restrict__ win,
                                                         BlkCtl* ctl) {
-    __shared__ long long red[kThreads / 64];
+    __shared__ ChunkLds chunks[kWaves];
+    __shared__ long long red[kWaves];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    ChunkLds* L = &chunks[wid];
     long long work = 0;
-    for (int v = blockIdx.x * kThreads + threadIdx.x; v < n; v += gridDim.x * kThreads) {
-        if (color[v] != 0) continue;
-        const int s = row_ptr[v], e = row_ptr[v + 1];
-        const int tv = tent[v];
+    const long long nchunks = ((long long)n + 63) / 64;
+    for (long long ch = (long long)blockIdx.x * kWaves + wid; ch < nchunks; ch += (long long)gridDim.x * kWaves) {
+        const int c0 = (int)(ch * 64);
+        const int c1 = (int)std::min<long long>(n, (long long)c0 + 64);
+        int total = 0, k = 0;
+        const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, L, lane, total, k);
+        if (mask == 0) continue;  // uniform
+        const int nU = __popcll(mask);
+        int acck = -1;
         bool lose = false;
-        for (int p0 = s; p0 < e && !lose; p0 += 4) {
-            int w[4], cw[4];
+        for (int jb = 0; jb < total; jb += 4 * 64) {
+            int o[4], w[4], c[4];
+            chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = p0 + j < e ? col_idx[p0 + j] : v;
+            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? tent[w[j]] : 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) cw[j] = color[w[j]];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (w[j] != v) lose |= (cw[j] != 0 ? cw[j] : tent[w[j]]) == tv && blk_before(key, w[j], v);
+            for (int j = 0; j < 4; ++j) {
+                if (o[j] < 0) continue;
+                if (o[j] != acck) {
+                    if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
+                    lose = false;
+                    acck = o[j];
+                }
+                const int v = c0 + L->qp[o[j]];
+                if (w[j] != v && c[j] == L->tv[o[j]] && blk_before(key, w[j], v)) lose = true;
+            }
         }
-        win[v] = lose ? 0 : 1;
-        work += e - s;
+        if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
+        wave_sync();
+        if ((mask >> lane) & 1) win[c0 + lane] = L->m[k] ? 0 : 1;
+        if (lane == 0) work += total;
+        wave_sync();  // the chunk state is rewritten by the next chunk
     }
     const long long t = blk_block_sum(work, red);
     if (threadIdx.x == 0 && t) atomicAdd((unsigned long long*)&ctl->work, (unsigned long long)t);
@@ -246,6 +435,11 @@ int grid_for(int dev, long long items) {
     return (int)std::max<long long>(1, std::min<long long>(want, (long long)cus * 8));
 }
 
+// Workgroups for one wavefront per item (the kernels stride past the cap).
+int wave_grid(long long items) {
+    return (int)std::max<long long>(1, std::min<long long>((items + kWaves - 1) / kWaves, 1 << 22));
+}
+
 }  // namespace
 
 extern "C" {
@@ -288,8 +482,13 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     gcolor_get_round_cap(&cap);
     const long long limit = cap > 0 ? cap : (long long)n + 64;
     const long long nblocks = ((long long)n + block_size - 1) / block_size;
-    const int vgrid = grid_for(dev, n), bgrid = grid_for(dev, nblocks * 64);  // kWaves blocks per workgroup
-    const size_t lds_bytes = sizeof(int) * (size_t)kWaves * (size_t)block_size;
+    const int vgrid = grid_for(dev, n);
+    // One wavefront per block (phase 1) and per 64-vertex chunk (phase 2): the
+    // dispatcher hands out workgroups as others finish, which evens out the
+    // degree skew of neighbouring id ranges that a fixed stride would gather
+    // onto the same wavefronts.
+    const int bgrid = wave_grid(nblocks), cgrid = wave_grid(((long long)n + 63) / 64);
+    const size_t lds_bytes = (size_t)kWaves * blk_wave_lds(block_size);
 
     k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, ctl);
     BLK_CHECK(hipGetLastError());
@@ -302,7 +501,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
             ++k;
             k_blk_first<<<bgrid, kThreads, lds_bytes, st>>>(n, block_size, nblocks, row_ptr, col_idx, colors_out,
                                                             tent);
-            k_blk_check<<<vgrid, kThreads, 0, st>>>(n, row_ptr, col_idx, priority, colors_out, tent, win, ctl);
+            k_blk_check<<<cgrid, kThreads, 0, st>>>(n, row_ptr, col_idx, priority, colors_out, tent, win, ctl);
             k_blk_commit<<<vgrid, kThreads, 0, st>>>(n, (int)k, colors_out, tent, win, ctl);
             BLK_CHECK(hipGetLastError());
         }
