@@ -10,8 +10,9 @@
 //     round (kept in LDS while the block is coloured, and written to tent);
 //   phase 2 (k_blk_check, one wavefront per 64 vertices): v in U loses when a
 //     neighbour holds its colour (tent for vertices of U, the committed
-//     colour otherwise) and precedes it in (key, id) order;
-//   phase 3 (k_blk_commit): winners commit, losers form U for round k+1.
+//     colour otherwise) and precedes it in (key, id) order; winners commit
+//     at once (this pass reads the committed colours of its own vertices
+//     only), losers form U for round k+1.
 // The kernel boundaries order the phases, so the result is a function of the
 // input and B.  B = 1 is Algorithm 2 itself; one block holding every vertex
 // is the serial greedy in index order, done in one round.  Every round
@@ -19,8 +20,8 @@
 // vertices needs at most n rounds.
 //
 // Memory: colors_out holds the committed colours (0 = uncoloured); the
-// workspace holds a 256-byte control block, tent (int32[n]) and the phase-2
-// verdicts (int32[n]).  Block sizes run from 1 to kMaxBlock (LDS per
+// workspace holds the round counters (64 slots of 128 bytes) and tent
+// (int32[n]).  Block sizes run from 1 to kMaxBlock (LDS per
 // wavefront of phase 1: 4 bytes per vertex of its block plus the state of
 // one 64-vertex chunk).
 //
@@ -45,27 +46,34 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxBlock = 2048;
 
-struct BlkCtl {
+// Round counters, spread over kSlots cache lines: workgroup b adds to slot
+// b % kSlots, so the one-wavefront-per-chunk grid (tens of thousands of
+// workgroups) does not queue its device-scope atomics on one address; the
+// host sums the slots.
+constexpr int kSlots = 64;
+struct BlkSlot {
     unsigned long long committed;  // vertices committed so far
     long long work;                // sum over rounds of the degrees of U
     int32_t rounds;                // last round that committed a vertex
     int32_t maxcolor;
-    int32_t pad[58];
+    int32_t pad[26];
 };
-static_assert(sizeof(BlkCtl) == 256, "control block");
+static_assert(sizeof(BlkSlot) == 128, "counter slot");
+struct BlkCtl {
+    BlkSlot slot[kSlots];
+};
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlkLayout {
-    size_t tent, win, total;
+    size_t tent, total;
 };
 
 BlkLayout blk_layout(int32_t n) {
     BlkLayout L;
     const size_t vn = sizeof(int32_t) * (size_t)(n > 0 ? n : 1);
     L.tent = align_up(sizeof(BlkCtl));
-    L.win = L.tent + align_up(vn);
-    L.total = L.win + align_up(vn);
+    L.total = L.tent + align_up(vn);
     return L;
 }
 
@@ -77,12 +85,8 @@ __device__ __forceinline__ bool blk_before(const uint32_t* __restrict__ key, int
 
 __global__ void k_blk_init(int n, int* __restrict__ color, BlkCtl* ctl) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i == 0) {
-        ctl->committed = 0;
-        ctl->work = 0;
-        ctl->rounds = 0;
-        ctl->maxcolor = 0;
-    }
+    int* c = reinterpret_cast<int*>(ctl);
+    for (int j = i; j < (int)(sizeof(BlkCtl) / sizeof(int)); j += gridDim.x * kThreads) c[j] = 0;
     for (int v = i; v < n; v += gridDim.x * kThreads) color[v] = 0;
 }
 
@@ -130,10 +134,10 @@ __host__ __device__ constexpr size_t blk_wave_lds(int B) {
 __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __restrict__ row_ptr,
                                                 const int* __restrict__ color, const int* __restrict__ tent,
                                                 ChunkLds* L, int lane, int& total, int& k) {
-    const int u = c0 + lane;
+    const int u = c0 + (lane < c1 - c0 ? lane : 0);
     int s = 0, e = 0;
     bool unc = false;
-    if (u < c1) {
+    if (lane < c1 - c0) {
         s = row_ptr[u];
         e = row_ptr[u + 1];
         unc = color[u] == 0;
@@ -238,8 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
     for (long long b = (long long)blockIdx.x * kWaves + wid; b < nblocks; b += (long long)gridDim.x * kWaves) {
         const int v0 = (int)(b * B);
         const int v1 = (int)std::min<long long>(n, (long long)v0 + B);
-        for (int c0 = v0; c0 < v1; c0 += 64) {
-            const int c1 = std::min(v1, c0 + 64);
+        for (long long cc0 = v0; cc0 < v1; cc0 += 64) {
+            const int c0 = (int)cc0, c1 = (int)std::min<long long>(v1, cc0 + 64);
             int total = 0, k = 0;
             const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, L, lane, total, k);
             if (mask == 0) continue;  // uniform
@@ -320,17 +324,16 @@ __device__ __forceinline__ long long blk_block_sum(long long x, long long* red) 
 // its uncoloured vertices.  tent holds every vertex's current colour: phase
 // 1 writes it for the uncoloured vertices only, and a vertex commits the
 // value it holds there, so one gather serves both kinds of neighbour.
-__global__ __launch_bounds__(kThreads) void k_blk_check(int n, const int* __restrict__ row_ptr,
+__global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
-                                                        const uint32_t* __restrict__ key,
-                                                        const int* __restrict__ color,
-                                                        const int* __restrict__ tent, int* __restrict__ win,
-                                                        BlkCtl* ctl) {
+                                                        const uint32_t* __restrict__ key, int* __restrict__ color,
+                                                        const int* __restrict__ tent, BlkCtl* ctl) {
     __shared__ ChunkLds chunks[kWaves];
     __shared__ long long red[kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     ChunkLds* L = &chunks[wid];
-    long long work = 0;
+    long long work = 0, ncom = 0;
+    int mx = 0;
     const long long nchunks = ((long long)n + 63) / 64;
     for (long long ch = (long long)blockIdx.x * kWaves + wid; ch < nchunks; ch += (long long)gridDim.x * kWaves) {
         const int c0 = (int)(ch * 64);
@@ -360,34 +363,34 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, const int* __rest
         }
         if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
         wave_sync();
-        if ((mask >> lane) & 1) win[c0 + lane] = L->m[k] ? 0 : 1;
+        if (((mask >> lane) & 1) && L->m[k] == 0) {  // a winner commits its choice
+            const int t = L->tv[k];
+            color[c0 + lane] = t;
+            mx = max(mx, t);
+            ++ncom;
+        }
         if (lane == 0) work += total;
         wave_sync();  // the chunk state is rewritten by the next chunk
     }
-    const long long t = blk_block_sum(work, red);
-    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long*)&ctl->work, (unsigned long long)t);
-}
-
-// Phase 3: winners commit.
-__global__ __launch_bounds__(kThreads) void k_blk_commit(int n, int k, int* __restrict__ color,
-                                                         const int* __restrict__ tent,
-                                                         const int* __restrict__ win, BlkCtl* ctl) {
-    __shared__ long long red[kThreads / 64];
-    long long c = 0;
-    int mx = 0;
-    for (int v = blockIdx.x * kThreads + threadIdx.x; v < n; v += gridDim.x * kThreads) {
-        if (color[v] != 0 || !win[v]) continue;
-        color[v] = tent[v];
-        mx = max(mx, tent[v]);
-        ++c;
-    }
+    // one update of this workgroup's slot: the work and commit sums share a
+    // word per wavefront (commits < 2^20 per workgroup), the largest colour
+    // its own
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
-    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&ctl->maxcolor, mx);
-    const long long t = blk_block_sum(c, red);
+    __shared__ int rmx[kWaves];
+    if (lane == 0) rmx[wid] = mx;
+    const long long t = blk_block_sum((work << 20) | ncom, red);
     if (threadIdx.x == 0 && t) {
-        atomicAdd(&ctl->committed, (unsigned long long)t);
-        atomicMax(&ctl->rounds, k);
+        BlkSlot* sl = &ctl->slot[blockIdx.x % kSlots];
+        int m = 0;
+        for (int i = 0; i < kWaves; ++i) m = max(m, rmx[i]);
+        const long long c = t & ((1 << 20) - 1);
+        atomicAdd((unsigned long long*)&sl->work, (unsigned long long)(t >> 20));
+        if (c) {
+            atomicAdd(&sl->committed, (unsigned long long)c);
+            atomicMax(&sl->rounds, round);
+            atomicMax(&sl->maxcolor, m);
+        }
     }
 }
 
@@ -416,11 +419,32 @@ int blk_workspace(int dev, size_t need, void** out) {
     return GCOLOR_OK;
 }
 
-// Per-thread pinned staging for the control block.
-BlkCtl* blk_host() {
-    thread_local BlkCtl* h = nullptr;
-    if (!h && hipHostMalloc((void**)&h, sizeof(BlkCtl), hipHostMallocDefault) != hipSuccess) h = nullptr;
+// Per-thread pinned staging for the counters and the entry count.
+struct BlkHost {
+    BlkCtl ctl;
+    int32_t nnz;
+};
+BlkHost* blk_host() {
+    thread_local BlkHost* h = nullptr;
+    if (!h && hipHostMalloc((void**)&h, sizeof(BlkHost), hipHostMallocDefault) != hipSuccess) h = nullptr;
     return h;
+}
+
+// Sums of the round counters over the slots.
+struct BlkTotals {
+    unsigned long long committed = 0;
+    long long work = 0;
+    int32_t rounds = 0, maxcolor = 0;
+};
+BlkTotals blk_totals(const BlkCtl& c) {
+    BlkTotals t;
+    for (int i = 0; i < kSlots; ++i) {
+        t.committed += c.slot[i].committed;
+        t.work += c.slot[i].work;
+        t.rounds = std::max(t.rounds, c.slot[i].rounds);
+        t.maxcolor = std::max(t.maxcolor, c.slot[i].maxcolor);
+    }
+    return t;
 }
 
 #define BLK_CHECK(x)                               \
@@ -457,11 +481,11 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     if (n == 0) return GCOLOR_OK;
     if (!row_ptr || !colors_out) return GCOLOR_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    BlkCtl* h = blk_host();
+    BlkHost* h = blk_host();
     if (!h) return GCOLOR_EHIP;
-    BLK_CHECK(hipMemcpyAsync(&h->pad[0], row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BLK_CHECK(hipMemcpyAsync(&h->nnz, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BLK_CHECK(hipStreamSynchronize(st));
-    const int64_t nnz = h->pad[0];
+    const int64_t nnz = h->nnz;
     if (nnz < 0) return GCOLOR_ECSR;
     if (nnz > 0 && !col_idx) return GCOLOR_EINVAL;
     int dev = 0;
@@ -477,7 +501,6 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     char* base = static_cast<char*>(ws);
     BlkCtl* ctl = reinterpret_cast<BlkCtl*>(base);
     int* tent = reinterpret_cast<int*>(base + L.tent);
-    int* win = reinterpret_cast<int*>(base + L.win);
     int32_t cap = 0;
     gcolor_get_round_cap(&cap);
     const long long limit = cap > 0 ? cap : (long long)n + 64;
@@ -495,31 +518,32 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     long long k = 0;
     int batch = 4;
     int rc = GCOLOR_OK;
+    BlkTotals tot;
     for (;;) {
         const long long nb = std::min<long long>(batch, limit - k);
         for (long long j = 0; j < nb; ++j) {
             ++k;
             k_blk_first<<<bgrid, kThreads, lds_bytes, st>>>(n, block_size, nblocks, row_ptr, col_idx, colors_out,
                                                             tent);
-            k_blk_check<<<cgrid, kThreads, 0, st>>>(n, row_ptr, col_idx, priority, colors_out, tent, win, ctl);
-            k_blk_commit<<<vgrid, kThreads, 0, st>>>(n, (int)k, colors_out, tent, win, ctl);
+            k_blk_check<<<cgrid, kThreads, 0, st>>>(n, (int)k, row_ptr, col_idx, priority, colors_out, tent, ctl);
             BLK_CHECK(hipGetLastError());
         }
-        BLK_CHECK(hipMemcpyAsync(h, ctl, sizeof(BlkCtl), hipMemcpyDeviceToHost, st));
+        BLK_CHECK(hipMemcpyAsync(&h->ctl, ctl, sizeof(BlkCtl), hipMemcpyDeviceToHost, st));
         BLK_CHECK(hipStreamSynchronize(st));
-        if (h->committed >= (unsigned long long)n) break;
+        tot = blk_totals(h->ctl);
+        if (tot.committed >= (unsigned long long)n) break;
         if (k >= limit) {
             rc = GCOLOR_EROUNDS;
             break;
         }
         batch = std::min(batch * 2, 16);
     }
-    if (rc == GCOLOR_OK && h->committed != (unsigned long long)n) rc = GCOLOR_EINTERNAL;
+    if (rc == GCOLOR_OK && tot.committed != (unsigned long long)n) rc = GCOLOR_EINTERNAL;
     if (stats) {
         if (rc == GCOLOR_OK) {
-            stats->rounds = h->rounds;
-            stats->num_colors = h->maxcolor;
-            stats->edge_work = h->work;
+            stats->rounds = tot.rounds;
+            stats->num_colors = tot.maxcolor;
+            stats->edge_work = tot.work;
         }
         stats->status = rc;
     }
