@@ -4,6 +4,8 @@ edge work (sum over rounds of the degrees of the uncoloured vertices) equal
 the oracle's on the same seeded inputs; block size 1 equals color_graph's
 colouring and one block equals the serial greedy in one round.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -135,3 +137,35 @@ def test_errors_workspace_and_round_cap():
 def test_rmat_scale20(block):
     """R-MAT scale 20, edge factor 8, (0.55, 0.1, 0.1, 0.25), natural order."""
     check(graphgen.rmat(20, 8, (0.55, 0.1, 0.1), 11), None, block, "rmat20")
+
+
+@functools.lru_cache(maxsize=None)
+def rmat24():
+    return graphgen.rmat(24, 8, (0.55, 0.1, 0.1), 11)
+
+
+def test_rmat_scale24_perm_every_vertex():
+    """R-MAT scale 24, edge factor 8, (0.55, 0.1, 0.1, 0.25), random
+    priorities, 64-vertex blocks (the benchmark's launch): every colour, the
+    rounds and the edge work equal the oracle's."""
+    g = rmat24()
+    check(g, graphgen.random_priority(g.n, 12), 64, "rmat24-perm")
+
+
+def test_rmat_scale24_natural_properties():
+    """The same graph in natural order, 64-vertex blocks: a proper colouring
+    with colour(v) <= deg(v) + 1, identical on a second call, its statistics
+    consistent with the colours.  (The oracle needs over a minute on one core
+    here; the vertex-by-vertex comparison in natural order runs at scale 20.)"""
+    g = rmat24()
+    print("case rmat24-natural properties n=%d nnz=%d" % (g.n, g.nnz), flush=True)
+    col, st = gpu_blocks(g, None, 64)
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    assert col.min() >= 1 and np.all(col <= deg + 1)
+    src = np.repeat(np.arange(g.n, dtype=np.int32), deg)
+    keep = src != g.col_idx
+    assert not np.any(col[src[keep]] == col[g.col_idx[keep]])
+    assert st.num_colors == int(col.max())
+    assert 1 <= st.rounds <= g.n and st.edge_work >= g.nnz
+    col2, st2 = gpu_blocks(g, None, 64)
+    assert np.array_equal(col, col2) and (st2.rounds, st2.edge_work) == (st.rounds, st.edge_work)
