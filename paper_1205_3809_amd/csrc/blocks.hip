@@ -20,8 +20,11 @@
 // vertices needs at most n rounds.
 //
 // Memory: colors_out holds the committed colours (0 = uncoloured); the
-// workspace holds the round counters (64 slots of 128 bytes) and tent
-// (int32[n]).  Block sizes run from 1 to kMaxBlock (LDS per
+// workspace holds the round counters (64 slots of 128 bytes), tent
+// (int32[n]) and byte copies of the committed and current colours, clamped
+// at 255 (c8, t8: uint8[n]).  The row walks gather the bytes: phase 1 only
+// needs "uncoloured" and the colours 1..64, phase 2 equality, which the
+// bytes decide unless both sides are 255 or more (then tent decides).  Block sizes run from 1 to kMaxBlock (LDS per
 // wavefront of phase 1: 4 bytes per vertex of its block plus the state of
 // one 64-vertex chunk).
 //
@@ -66,14 +69,17 @@ struct BlkCtl {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlkLayout {
-    size_t tent, total;
+    size_t tent, c8, t8, total;
 };
 
 BlkLayout blk_layout(int32_t n) {
     BlkLayout L;
     const size_t vn = sizeof(int32_t) * (size_t)(n > 0 ? n : 1);
     L.tent = align_up(sizeof(BlkCtl));
-    L.total = L.tent + align_up(vn);
+    const size_t bn = (size_t)(n > 0 ? n : 1);
+    L.c8 = L.tent + align_up(vn);
+    L.t8 = L.c8 + align_up(bn);
+    L.total = L.t8 + align_up(bn);
     return L;
 }
 
@@ -83,11 +89,16 @@ __device__ __forceinline__ bool blk_before(const uint32_t* __restrict__ key, int
     return kw < kv || (kw == kv && w < v);
 }
 
-__global__ void k_blk_init(int n, int* __restrict__ color, BlkCtl* ctl) {
+__device__ __forceinline__ uint8_t blk_byte(int c) { return (uint8_t)min(c, 255); }
+
+__global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__ c8, BlkCtl* ctl) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     int* c = reinterpret_cast<int*>(ctl);
     for (int j = i; j < (int)(sizeof(BlkCtl) / sizeof(int)); j += gridDim.x * kThreads) c[j] = 0;
-    for (int v = i; v < n; v += gridDim.x * kThreads) color[v] = 0;
+    for (int v = i; v < n; v += gridDim.x * kThreads) {
+        color[v] = 0;
+        c8[v] = 0;
+    }
 }
 
 // Colour of neighbour w as vertex v (block starting at v0) sees it in
@@ -233,7 +244,9 @@ __device__ int blk_first_fit(int v, int v0, int base, const int* __restrict__ ro
 __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long nblocks,
                                                         const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
-                                                        const int* __restrict__ color, int* __restrict__ tent) {
+                                                        const int* __restrict__ color,
+                                                        const uint8_t* __restrict__ c8, int* __restrict__ tent,
+                                                        uint8_t* __restrict__ t8) {
     extern __shared__ unsigned long long lds64[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     char* wbase = reinterpret_cast<char*>(lds64) + (size_t)wid * blk_wave_lds(B);
@@ -254,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                 int o[4], w[4], c[4];
                 chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? color[w[j]] : 0;
+                for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? c8[w[j]] : 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (o[j] < 0) continue;
@@ -302,6 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
             if (unc) {
                 lt[c0 - v0 + lane] = t;
                 tent[c0 + lane] = t;
+                t8[c0 + lane] = blk_byte(t);
             }
             wave_sync();  // the chunk state and lt are read by the next chunk
         }
@@ -327,7 +341,9 @@ __device__ __forceinline__ long long blk_block_sum(long long x, long long* red) 
 __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
                                                         const uint32_t* __restrict__ key, int* __restrict__ color,
-                                                        const int* __restrict__ tent, BlkCtl* ctl) {
+                                                        const int* __restrict__ tent,
+                                                        const uint8_t* __restrict__ t8, uint8_t* __restrict__ c8,
+                                                        BlkCtl* ctl) {
     __shared__ ChunkLds chunks[kWaves];
     __shared__ long long red[kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -348,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
             int o[4], w[4], c[4];
             chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? tent[w[j]] : 0;
+            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? t8[w[j]] : 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (o[j] < 0) continue;
@@ -358,7 +374,10 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
                     acck = o[j];
                 }
                 const int v = c0 + L->qp[o[j]];
-                if (w[j] != v && c[j] == L->tv[o[j]] && blk_before(key, w[j], v)) lose = true;
+                const int tv = L->tv[o[j]];
+                if (w[j] != v && c[j] == (int)blk_byte(tv) && (tv < 255 || tent[w[j]] == tv) &&
+                    blk_before(key, w[j], v))
+                    lose = true;
             }
         }
         if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
@@ -366,6 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         if (((mask >> lane) & 1) && L->m[k] == 0) {  // a winner commits its choice
             const int t = L->tv[k];
             color[c0 + lane] = t;
+            c8[c0 + lane] = blk_byte(t);
             mx = max(mx, t);
             ++ncom;
         }
@@ -501,6 +521,8 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     char* base = static_cast<char*>(ws);
     BlkCtl* ctl = reinterpret_cast<BlkCtl*>(base);
     int* tent = reinterpret_cast<int*>(base + L.tent);
+    uint8_t* c8 = reinterpret_cast<uint8_t*>(base + L.c8);
+    uint8_t* t8 = reinterpret_cast<uint8_t*>(base + L.t8);
     int32_t cap = 0;
     gcolor_get_round_cap(&cap);
     const long long limit = cap > 0 ? cap : (long long)n + 64;
@@ -513,7 +535,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     const int bgrid = wave_grid(nblocks), cgrid = wave_grid(((long long)n + 63) / 64);
     const size_t lds_bytes = (size_t)kWaves * blk_wave_lds(block_size);
 
-    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, ctl);
+    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, c8, ctl);
     BLK_CHECK(hipGetLastError());
     long long k = 0;
     int batch = 4;
@@ -524,8 +546,9 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
         for (long long j = 0; j < nb; ++j) {
             ++k;
             k_blk_first<<<bgrid, kThreads, lds_bytes, st>>>(n, block_size, nblocks, row_ptr, col_idx, colors_out,
-                                                            tent);
-            k_blk_check<<<cgrid, kThreads, 0, st>>>(n, (int)k, row_ptr, col_idx, priority, colors_out, tent, ctl);
+                                                            c8, tent, t8);
+            k_blk_check<<<cgrid, kThreads, 0, st>>>(n, (int)k, row_ptr, col_idx, priority, colors_out, tent, t8, c8,
+                                                  ctl);
             BLK_CHECK(hipGetLastError());
         }
         BLK_CHECK(hipMemcpyAsync(&h->ctl, ctl, sizeof(BlkCtl), hipMemcpyDeviceToHost, st));

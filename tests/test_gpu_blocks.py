@@ -66,6 +66,16 @@ def test_structured(block):
     check(graphgen.rgg(20000, 12.0, 4), None, block, "rgg")
 
 
+@pytest.mark.parametrize("block", [1, 7, 64, 2048])
+def test_colours_past_255(block):
+    """K_600 takes colours 1..600: the byte copies of the colours clamp at 255,
+    so conflicts between colours of 255 and more (300 against 400, say) are
+    told apart by the full values."""
+    g = graphgen.complete(600)
+    check(g, None, block, "complete600")
+    check(g, graphgen.random_priority(g.n, 5), block, "complete600-perm")
+
+
 def test_block_one_is_color_graph():
     import paper_1205_3809_amd as gc
     g = graphgen.rmat(15, 8, (0.55, 0.1, 0.1), 5)
