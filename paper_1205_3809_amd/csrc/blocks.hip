@@ -24,14 +24,15 @@
 // (int32[n]) and byte copies of the committed and current colours, clamped
 // at 255 (c8, t8: uint8[n]).  The row walks gather the bytes: phase 1 only
 // needs "uncoloured" and the colours 1..64, phase 2 equality, which the
-// bytes decide unless both sides are 255 or more (then tent decides).  Block sizes run from 1 to kMaxBlock (LDS per
-// wavefront of phase 1: 4 bytes per vertex of its block plus the state of
-// one 64-vertex chunk).
+// bytes decide unless both sides are 255 or more (then tent decides).
+// Block sizes run from 1 to kMaxBlock (LDS per wavefront of phase 1: 4 bytes
+// per vertex of its block plus the state of one 64-vertex chunk).
 //
 // Both row passes work on chunks of 64 consecutive vertices: a wavefront
 // compacts the chunk's vertices of U, prefix-sums their degrees and walks
-// their rows as one concatenated range, 64 entries per step, so a hub row is
-// spread over every lane and light rows share a step.
+// their rows as one concatenated range, 256 entries per step (four
+// consecutive ones per lane), so a hub row is spread over every lane and
+// light rows share a step.
 
 #include <hip/hip_runtime.h>
 
