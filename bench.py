@@ -221,7 +221,8 @@ def bench_blocks(args):
     # algorithmic bytes of one colouring: per round, both row passes read
     # neighbour id + colour (8 B) per entry of an uncoloured row and each
     # reads the row_ptr pair and colour of every vertex of its chunks
-    # (2 x 12 B per vertex); the commits write each colour once
+    # (2 x 12 B per vertex); the commits write each colour once (without
+    # priorities phase 2 gathers only for the smaller ids: counted in full)
     algo = 16 * st.edge_work + 24 * g.n * st.rounds + 4 * g.n
     achieved = algo / (ev_ms / 1e3) / 1e9
     roofline = {"kernel": "whole call (k_blk_first + k_blk_check)", "bound": "hbm",

@@ -364,8 +364,13 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         for (int jb = 0; jb < total; jb += 4 * 64) {
             int o[4], w[4], c[4];
             chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
+            int vv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? t8[w[j]] : 0;
+            for (int j = 0; j < 4; ++j) vv[j] = o[j] >= 0 ? c0 + L->qp[o[j]] : 0;
+            // without priorities only a smaller id can precede: the other
+            // entries need no gather (their c stays 0, below every colour)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 && (key || w[j] < vv[j]) ? t8[w[j]] : 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (o[j] < 0) continue;
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
                     lose = false;
                     acck = o[j];
                 }
-                const int v = c0 + L->qp[o[j]];
+                const int v = vv[j];
                 const int tv = L->tv[o[j]];
                 if (w[j] != v && c[j] == (int)blk_byte(tv) && (tv < 255 || tent[w[j]] == tv) &&
                     blk_before(key, w[j], v))
