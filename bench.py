@@ -229,6 +229,22 @@ def bench_blocks(args):
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_step": int(algo)}
+    # the block oracle (one core) on the same workload: baseline and parity;
+    # the serial greedy for the colour count
+    cpu = None
+    parity = None
+    greedy_colors = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.block_gs(g.row_ptr, g.col_idx, key, B)
+        dt = time.perf_counter() - t
+        parity = bool(np.array_equal(ref.colors, out.cpu().numpy())) and ref.rounds == st.rounds
+        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload (%.1f s)" % dt}
+        greedy_colors = int(oracle.greedy(g.row_ptr, g.col_idx, key).max())
+        log("block oracle %.1fs parity=%s; serial greedy %d colours" % (dt, parity, greedy_colors))
+
     p = WORKLOADS[args.workload][1]
     config = {"workload": "%s-%s" % (args.workload, args.order), "engine": "blocks", "block_size": B,
               "n": g.n, "nnz": g.nnz, "edges": g.edges}
@@ -238,9 +254,9 @@ def bench_blocks(args):
         "value": round(g.edges / (ms_per_step / 1e3), 1), "unit": "edges/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic", "config": config, "colors": int(st.num_colors), "rounds": int(st.rounds),
-        "edge_work_over_nnz": round(st.edge_work / max(g.nnz, 1), 3), "parity_vs_oracle": None,
-        "roofline": roofline, "cpu_baseline": None,
+        "data": "synthetic", "config": config, "colors": int(st.num_colors), "serial_greedy_colors": greedy_colors,
+        "rounds": int(st.rounds), "edge_work_over_nnz": round(st.edge_work / max(g.nnz, 1), 3),
+        "parity_vs_oracle": parity, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
 
