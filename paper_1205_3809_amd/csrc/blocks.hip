@@ -12,7 +12,8 @@
 //     neighbour holds its colour (tent for vertices of U, the committed
 //     colour otherwise) and precedes it in (key, id) order; winners commit
 //     at once (this pass reads the committed colours of its own vertices
-//     only), losers form U for round k+1.
+//     only) and OR their colour into their neighbours' masks of committed
+//     colours; losers form U for round k+1.
 // The kernel boundaries order the phases, so the result is a function of the
 // input and B.  B = 1 is Algorithm 2 itself; one block holding every vertex
 // is the serial greedy in index order, done in one round.  Every round
@@ -21,10 +22,13 @@
 //
 // Memory: colors_out holds the committed colours (0 = uncoloured); the
 // workspace holds the round counters (64 slots of 128 bytes), tent
-// (int32[n]) and byte copies of the committed and current colours, clamped
-// at 255 (c8, t8: uint8[n]).  The row walks gather the bytes: phase 1 only
-// needs "uncoloured" and the colours 1..64, phase 2 equality, which the
-// bytes decide unless both sides are 255 or more (then tent decides).
+// (int32[n]), byte copies of the committed and current colours, clamped at
+// 255 (c8, t8: uint8[n]), and per vertex the mask of its neighbours'
+// committed colours 1..64 (fm: uint64[n]).  Phase 1 takes the committed
+// colours from fm and walks a row only for the neighbours inside the block;
+// a vertex with 1..64 all taken scans its row with the int32 colours.
+// Phase 2 gathers the bytes: equal bytes are equal colours unless both
+// sides are 255 or more (then tent decides).
 // Block sizes run from 1 to kMaxBlock (LDS per wavefront of phase 1: 4 bytes
 // per vertex of its block plus the state of one 64-vertex chunk).
 //
@@ -70,7 +74,7 @@ struct BlkCtl {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlkLayout {
-    size_t tent, c8, t8, total;
+    size_t tent, c8, t8, fm, total;
 };
 
 BlkLayout blk_layout(int32_t n) {
@@ -80,7 +84,8 @@ BlkLayout blk_layout(int32_t n) {
     const size_t bn = (size_t)(n > 0 ? n : 1);
     L.c8 = L.tent + align_up(vn);
     L.t8 = L.c8 + align_up(bn);
-    L.total = L.t8 + align_up(bn);
+    L.fm = L.t8 + align_up(bn);
+    L.total = L.fm + align_up(sizeof(unsigned long long) * bn);
     return L;
 }
 
@@ -92,13 +97,15 @@ __device__ __forceinline__ bool blk_before(const uint32_t* __restrict__ key, int
 
 __device__ __forceinline__ uint8_t blk_byte(int c) { return (uint8_t)min(c, 255); }
 
-__global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__ c8, BlkCtl* ctl) {
+__global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__ c8,
+                           unsigned long long* __restrict__ fm, BlkCtl* ctl) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     int* c = reinterpret_cast<int*>(ctl);
     for (int j = i; j < (int)(sizeof(BlkCtl) / sizeof(int)); j += gridDim.x * kThreads) c[j] = 0;
     for (int v = i; v < n; v += gridDim.x * kThreads) {
         color[v] = 0;
         c8[v] = 0;
+        fm[v] = 0;
     }
 }
 
@@ -133,19 +140,22 @@ struct ChunkLds {
 };
 static_assert(sizeof(ChunkLds) % 8 == 0, "chunk LDS alignment");
 
-// LDS of one wavefront of k_blk_first: its chunk state, then one int per
-// vertex of its block.
+// LDS of one wavefront of k_blk_first: its chunk state, one int per vertex
+// of its block (the choices), then one bit per vertex of its block (still
+// uncoloured at the start of the round).
+__host__ __device__ constexpr size_t blk_lt_bytes(int B) { return ((size_t)B * sizeof(int) + 7) & ~(size_t)7; }
 __host__ __device__ constexpr size_t blk_wave_lds(int B) {
-    return sizeof(ChunkLds) + (((size_t)B * sizeof(int) + 7) & ~(size_t)7);
+    return sizeof(ChunkLds) + blk_lt_bytes(B) + sizeof(unsigned long long) * (((size_t)B + 63) / 64);
 }
 
 // Sets up the chunk [c0, c1): returns the mask of its uncoloured vertices
 // (bit q = vertex c0 + q); for them fills pre/rs/qp (and tv from tent when
-// tent is given) and clears m and d.  total = the sum of their degrees, k =
+// tent is given), clears d and sets m to fm (0 without fm).  total = the sum of their degrees, k =
 // the calling lane's rank among them.  Uniform over the wavefront.
 __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __restrict__ row_ptr,
                                                 const int* __restrict__ color, const int* __restrict__ tent,
-                                                ChunkLds* L, int lane, int& total, int& k) {
+                                                const unsigned long long* __restrict__ fm, ChunkLds* L, int lane,
+                                                int& total, int& k) {
     const int u = c0 + (lane < c1 - c0 ? lane : 0);
     int s = 0, e = 0;
     bool unc = false;
@@ -169,7 +179,7 @@ __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __res
         L->pre[k] = x - deg;
         L->rs[k] = s;
         L->qp[k] = lane;
-        L->m[k] = 0;
+        L->m[k] = fm ? fm[u] : 0;
         L->d[k] = 0;
         if (tent) L->tv[k] = tent[u];
     }
@@ -246,29 +256,34 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                                                         const int* __restrict__ row_ptr,
                                                         const int* __restrict__ col_idx,
                                                         const int* __restrict__ color,
-                                                        const uint8_t* __restrict__ c8, int* __restrict__ tent,
-                                                        uint8_t* __restrict__ t8) {
+                                                        const uint8_t* __restrict__ c8,
+                                                        const unsigned long long* __restrict__ fm,
+                                                        int* __restrict__ tent, uint8_t* __restrict__ t8) {
     extern __shared__ unsigned long long lds64[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     char* wbase = reinterpret_cast<char*>(lds64) + (size_t)wid * blk_wave_lds(B);
     ChunkLds* L = reinterpret_cast<ChunkLds*>(wbase);
     int* lt = reinterpret_cast<int*>(wbase + sizeof(ChunkLds));
+    unsigned long long* ub = reinterpret_cast<unsigned long long*>(wbase + sizeof(ChunkLds) + blk_lt_bytes(B));
     for (long long b = (long long)blockIdx.x * kWaves + wid; b < nblocks; b += (long long)gridDim.x * kWaves) {
         const int v0 = (int)(b * B);
         const int v1 = (int)std::min<long long>(n, (long long)v0 + B);
+        for (int i0 = 0; i0 < v1 - v0; i0 += 64) {  // which of the block's vertices are uncoloured
+            const unsigned long long bits = __ballot(i0 + lane < v1 - v0 && c8[v0 + i0 + lane] == 0);
+            if (lane == 0) ub[i0 >> 6] = bits;
+        }
+        wave_sync();
         for (long long cc0 = v0; cc0 < v1; cc0 += 64) {
             const int c0 = (int)cc0, c1 = (int)std::min<long long>(v1, cc0 + 64);
             int total = 0, k = 0;
-            const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, L, lane, total, k);
+            const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, fm, L, lane, total, k);
             if (mask == 0) continue;  // uniform
             const int nU = __popcll(mask);
             int acck = -1;
             uint64_t am = 0, ad = 0;
             for (int jb = 0; jb < total; jb += 4 * 64) {
-                int o[4], w[4], c[4];
+                int o[4], w[4];
                 chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 ? c8[w[j]] : 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (o[j] < 0) continue;
@@ -280,17 +295,17 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                         am = ad = 0;
                         acck = o[j];
                     }
-                    const int v = c0 + L->qp[o[j]];
-                    if (w[j] == v) continue;
-                    int cc = c[j];
-                    if (cc == 0) {
-                        if (w[j] >= v0 && w[j] < c0) {
-                            cc = lt[w[j] - v0];
-                        } else if (w[j] >= c0 && w[j] < v) {
-                            ad |= 1ull << (w[j] - c0);
-                            continue;
-                        }
+                    // committed neighbours are in fm already; what is left
+                    // is the block's uncoloured vertices before v
+                    const int v = c0 + L->qp[o[j]], x = w[j];
+                    if (x == v || x < v0 || x >= v) continue;
+                    const int i = x - v0;
+                    if (!((ub[i >> 6] >> (i & 63)) & 1)) continue;
+                    if (x >= c0) {
+                        ad |= 1ull << (x - c0);
+                        continue;
                     }
+                    const int cc = lt[i];
                     if ((unsigned)(cc - 1) < 64u) am |= 1ull << (cc - 1);
                 }
             }
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
                                                         const uint32_t* __restrict__ key, int* __restrict__ color,
                                                         const int* __restrict__ tent,
                                                         const uint8_t* __restrict__ t8, uint8_t* __restrict__ c8,
-                                                        BlkCtl* ctl) {
+                                                        unsigned long long* __restrict__ fm, BlkCtl* ctl) {
     __shared__ ChunkLds chunks[kWaves];
     __shared__ long long red[kWaves];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -356,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         const int c0 = (int)(ch * 64);
         const int c1 = (int)std::min<long long>(n, (long long)c0 + 64);
         int total = 0, k = 0;
-        const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, L, lane, total, k);
+        const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, nullptr, L, lane, total, k);
         if (mask == 0) continue;  // uniform
         const int nU = __popcll(mask);
         int acck = -1;
@@ -388,14 +403,52 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         }
         if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
         wave_sync();
-        if (((mask >> lane) & 1) && L->m[k] == 0) {  // a winner commits its choice
-            const int t = L->tv[k];
+        const bool won = ((mask >> lane) & 1) && L->m[k] == 0;
+        int t = 0;
+        if (won) {  // a winner commits its choice
+            t = L->tv[k];
             color[c0 + lane] = t;
             c8[c0 + lane] = blk_byte(t);
             mx = max(mx, t);
             ++ncom;
         }
         if (lane == 0) work += total;
+        // the winners put their colour (when at most 64) into the masks of
+        // their neighbours, walking their rows as one concatenated range
+        const uint64_t wmask = __ballot(won && t <= 64);
+        wave_sync();  // the chunk state is rewritten below
+        if (wmask) {
+            int s = 0, e = 0;
+            if ((wmask >> lane) & 1) {
+                s = row_ptr[c0 + lane];
+                e = row_ptr[c0 + lane + 1];
+            }
+            const int deg = e - s;
+            int x = deg;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            const int wtotal = __shfl(x, 63), nW = __popcll(wmask);
+            if ((wmask >> lane) & 1) {
+                const int r = __popcll(wmask & ((1ull << lane) - 1));
+                L->pre[r] = x - deg;
+                L->rs[r] = s;
+                L->qp[r] = lane;
+                L->tv[r] = t;
+            }
+            if (lane == 0) L->pre[nW] = wtotal;
+            wave_sync();
+            for (int jb = 0; jb < wtotal; jb += 4 * 64) {
+                int o[4], w[4];
+                chunk_entries(L, nW, wtotal, jb + 4 * lane, col_idx, o, w);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (o[j] >= 0 && w[j] != c0 + L->qp[o[j]])
+                        atomicOr(&fm[w[j]], 1ull << (L->tv[o[j]] - 1));
+            }
+        }
         wave_sync();  // the chunk state is rewritten by the next chunk
     }
     // one update of this workgroup's slot: the work and commit sums share a
@@ -529,6 +582,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     int* tent = reinterpret_cast<int*>(base + L.tent);
     uint8_t* c8 = reinterpret_cast<uint8_t*>(base + L.c8);
     uint8_t* t8 = reinterpret_cast<uint8_t*>(base + L.t8);
+    unsigned long long* fm = reinterpret_cast<unsigned long long*>(base + L.fm);
     int32_t cap = 0;
     gcolor_get_round_cap(&cap);
     const long long limit = cap > 0 ? cap : (long long)n + 64;
@@ -541,7 +595,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     const int bgrid = wave_grid(nblocks), cgrid = wave_grid(((long long)n + 63) / 64);
     const size_t lds_bytes = (size_t)kWaves * blk_wave_lds(block_size);
 
-    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, c8, ctl);
+    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, c8, fm, ctl);
     BLK_CHECK(hipGetLastError());
     long long k = 0;
     int batch = 4;
@@ -552,9 +606,9 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
         for (long long j = 0; j < nb; ++j) {
             ++k;
             k_blk_first<<<bgrid, kThreads, lds_bytes, st>>>(n, block_size, nblocks, row_ptr, col_idx, colors_out,
-                                                            c8, tent, t8);
+                                                            c8, fm, tent, t8);
             k_blk_check<<<cgrid, kThreads, 0, st>>>(n, (int)k, row_ptr, col_idx, priority, colors_out, tent, t8, c8,
-                                                  ctl);
+                                                  fm, ctl);
             BLK_CHECK(hipGetLastError());
         }
         BLK_CHECK(hipMemcpyAsync(&h->ctl, ctl, sizeof(BlkCtl), hipMemcpyDeviceToHost, st));
