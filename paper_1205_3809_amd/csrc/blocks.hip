@@ -374,34 +374,28 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, nullptr, L, lane, total, k);
         if (mask == 0) continue;  // uniform
         const int nU = __popcll(mask);
-        int acck = -1;
-        bool lose = false;
         for (int jb = 0; jb < total; jb += 4 * 64) {
-            int o[4], w[4], c[4];
+            int o[4], w[4], c[4], vv[4];
+            bool need[4];
             chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
-            int vv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) vv[j] = o[j] >= 0 ? c0 + L->qp[o[j]] : 0;
-            // without priorities only a smaller id can precede: the other
-            // entries need no gather (their c stays 0, below every colour)
+            // without priorities only a smaller id can precede; a vertex that
+            // has lost already needs no more gathers
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] = o[j] >= 0 && (key || w[j] < vv[j]) ? t8[w[j]] : 0;
+            for (int j = 0; j < 4; ++j) need[j] = o[j] >= 0 && (key || w[j] < vv[j]) && L->m[o[j]] == 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = need[j] ? t8[w[j]] : 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (o[j] < 0) continue;
-                if (o[j] != acck) {
-                    if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
-                    lose = false;
-                    acck = o[j];
-                }
+                if (!need[j]) continue;
                 const int v = vv[j];
                 const int tv = L->tv[o[j]];
                 if (w[j] != v && c[j] == (int)blk_byte(tv) && (tv < 255 || tent[w[j]] == tv) &&
                     blk_before(key, w[j], v))
-                    lose = true;
+                    atomicOr(&L->m[o[j]], 1ull);
             }
         }
-        if (acck >= 0 && lose) atomicOr(&L->m[acck], 1ull);
         wave_sync();
         const bool won = ((mask >> lane) & 1) && L->m[k] == 0;
         int t = 0;
