@@ -23,9 +23,11 @@
 // Memory: colors_out holds the committed colours (0 = uncoloured); the
 // workspace holds the round counters (64 slots of 128 bytes), tent
 // (int32[n]), byte copies of the committed and current colours, clamped at
-// 255 (c8, t8: uint8[n]), and per vertex the mask of its neighbours'
-// committed colours 1..64 (fm: uint64[n]).  Phase 1 takes the committed
-// colours from fm and walks a row only for the neighbours inside the block;
+// 255 (c8, t8: uint8[n]), per vertex whether it may have a neighbour
+// earlier in its block (hp: uint8[n], decided by the first walk of its row)
+// and the mask of its neighbours' committed colours 1..64 (fm: uint64[n]).
+// Phase 1 takes the committed colours from fm and walks a row only for the
+// neighbours inside the block, and only while hp is set;
 // a vertex with 1..64 all taken scans its row with the int32 colours.
 // Phase 2 gathers the bytes: equal bytes are equal colours unless both
 // sides are 255 or more (then tent decides).
@@ -74,7 +76,7 @@ struct BlkCtl {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlkLayout {
-    size_t tent, c8, t8, fm, total;
+    size_t tent, c8, t8, hp, fm, total;
 };
 
 BlkLayout blk_layout(int32_t n) {
@@ -84,7 +86,8 @@ BlkLayout blk_layout(int32_t n) {
     const size_t bn = (size_t)(n > 0 ? n : 1);
     L.c8 = L.tent + align_up(vn);
     L.t8 = L.c8 + align_up(bn);
-    L.fm = L.t8 + align_up(bn);
+    L.hp = L.t8 + align_up(bn);
+    L.fm = L.hp + align_up(bn);
     L.total = L.fm + align_up(sizeof(unsigned long long) * bn);
     return L;
 }
@@ -97,7 +100,7 @@ __device__ __forceinline__ bool blk_before(const uint32_t* __restrict__ key, int
 
 __device__ __forceinline__ uint8_t blk_byte(int c) { return (uint8_t)min(c, 255); }
 
-__global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__ c8,
+__global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__ c8, uint8_t* __restrict__ hp,
                            unsigned long long* __restrict__ fm, BlkCtl* ctl) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     int* c = reinterpret_cast<int*>(ctl);
@@ -105,6 +108,7 @@ __global__ void k_blk_init(int n, int* __restrict__ color, uint8_t* __restrict__
     for (int v = i; v < n; v += gridDim.x * kThreads) {
         color[v] = 0;
         c8[v] = 0;
+        hp[v] = 1;  // not known yet: the first walk of the row decides
         fm[v] = 0;
     }
 }
@@ -136,6 +140,7 @@ struct ChunkLds {
     int rs[64];
     int qp[64];
     int tv[64];
+    int hpf[64];  // phase 1: a neighbour earlier in the same block was seen
     int pad[3];
 };
 static_assert(sizeof(ChunkLds) % 8 == 0, "chunk LDS alignment");
@@ -150,12 +155,14 @@ __host__ __device__ constexpr size_t blk_wave_lds(int B) {
 
 // Sets up the chunk [c0, c1): returns the mask of its uncoloured vertices
 // (bit q = vertex c0 + q); for them fills pre/rs/qp (and tv from tent when
-// tent is given), clears d and sets m to fm (0 without fm).  total = the sum of their degrees, k =
+// tent is given), clears d and hpf and sets m to fm (0 without fm); with hp,
+// the rows of vertices whose hp is 0 are left out of the walk.  total = the sum of their degrees, k =
 // the calling lane's rank among them.  Uniform over the wavefront.
 __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __restrict__ row_ptr,
                                                 const int* __restrict__ color, const int* __restrict__ tent,
-                                                const unsigned long long* __restrict__ fm, ChunkLds* L, int lane,
-                                                int& total, int& k) {
+                                                const unsigned long long* __restrict__ fm,
+                                                const uint8_t* __restrict__ hp, ChunkLds* L, int lane, int& total,
+                                                int& k) {
     const int u = c0 + (lane < c1 - c0 ? lane : 0);
     int s = 0, e = 0;
     bool unc = false;
@@ -166,7 +173,9 @@ __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __res
     }
     const uint64_t mask = __ballot(unc);
     if (mask == 0) return 0;
-    const int deg = unc ? e - s : 0;
+    // with hp, a row is walked only while it may hold a neighbour earlier in
+    // the block (rows of the others count as empty)
+    const int deg = unc && (!hp || hp[u]) ? e - s : 0;
     int x = deg;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -181,6 +190,7 @@ __device__ __forceinline__ uint64_t chunk_setup(int c0, int c1, const int* __res
         L->qp[k] = lane;
         L->m[k] = fm ? fm[u] : 0;
         L->d[k] = 0;
+        L->hpf[k] = 0;
         if (tent) L->tv[k] = tent[u];
     }
     if (lane == 0) L->pre[__popcll(mask)] = total;
@@ -258,7 +268,8 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                                                         const int* __restrict__ color,
                                                         const uint8_t* __restrict__ c8,
                                                         const unsigned long long* __restrict__ fm,
-                                                        int* __restrict__ tent, uint8_t* __restrict__ t8) {
+                                                        uint8_t* __restrict__ hp, int* __restrict__ tent,
+                                                        uint8_t* __restrict__ t8) {
     extern __shared__ unsigned long long lds64[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     char* wbase = reinterpret_cast<char*>(lds64) + (size_t)wid * blk_wave_lds(B);
@@ -276,11 +287,12 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
         for (long long cc0 = v0; cc0 < v1; cc0 += 64) {
             const int c0 = (int)cc0, c1 = (int)std::min<long long>(v1, cc0 + 64);
             int total = 0, k = 0;
-            const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, fm, L, lane, total, k);
+            const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, nullptr, fm, hp, L, lane, total, k);
             if (mask == 0) continue;  // uniform
             const int nU = __popcll(mask);
             int acck = -1;
             uint64_t am = 0, ad = 0;
+            bool ahp = false;
             for (int jb = 0; jb < total; jb += 4 * 64) {
                 int o[4], w[4];
                 chunk_entries(L, nU, total, jb + 4 * lane, col_idx, o, w);
@@ -291,14 +303,17 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                         if (acck >= 0) {
                             if (am) atomicOr(&L->m[acck], am);
                             if (ad) atomicOr(&L->d[acck], ad);
+                            if (ahp) L->hpf[acck] = 1;
                         }
                         am = ad = 0;
+                        ahp = false;
                         acck = o[j];
                     }
                     // committed neighbours are in fm already; what is left
                     // is the block's uncoloured vertices before v
                     const int v = c0 + L->qp[o[j]], x = w[j];
                     if (x == v || x < v0 || x >= v) continue;
+                    ahp = true;
                     const int i = x - v0;
                     if (!((ub[i >> 6] >> (i & 63)) & 1)) continue;
                     if (x >= c0) {
@@ -312,6 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
             if (acck >= 0) {
                 if (am) atomicOr(&L->m[acck], am);
                 if (ad) atomicOr(&L->d[acck], ad);
+                if (ahp) L->hpf[acck] = 1;
             }
             wave_sync();
             const bool unc = (mask >> lane) & 1;
@@ -329,6 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_first(int n, int B, long long 
                 if (((dep >> q) & 1) && tq <= 64) F |= 1ull << (tq - 1);
             }
             if (unc) {
+                if (hp[c0 + lane] && !L->hpf[k]) hp[c0 + lane] = 0;  // walked: none earlier in the block
                 lt[c0 - v0 + lane] = t;
                 tent[c0 + lane] = t;
                 t8[c0 + lane] = blk_byte(t);
@@ -371,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_blk_check(int n, int round, const 
         const int c0 = (int)(ch * 64);
         const int c1 = (int)std::min<long long>(n, (long long)c0 + 64);
         int total = 0, k = 0;
-        const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, nullptr, L, lane, total, k);
+        const uint64_t mask = chunk_setup(c0, c1, row_ptr, color, tent, nullptr, nullptr, L, lane, total, k);
         if (mask == 0) continue;  // uniform
         const int nU = __popcll(mask);
         for (int jb = 0; jb < total; jb += 4 * 64) {
@@ -577,6 +594,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     uint8_t* c8 = reinterpret_cast<uint8_t*>(base + L.c8);
     uint8_t* t8 = reinterpret_cast<uint8_t*>(base + L.t8);
     unsigned long long* fm = reinterpret_cast<unsigned long long*>(base + L.fm);
+    uint8_t* hp = reinterpret_cast<uint8_t*>(base + L.hp);
     int32_t cap = 0;
     gcolor_get_round_cap(&cap);
     const long long limit = cap > 0 ? cap : (long long)n + 64;
@@ -589,7 +607,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     const int bgrid = wave_grid(nblocks), cgrid = wave_grid(((long long)n + 63) / 64);
     const size_t lds_bytes = (size_t)kWaves * blk_wave_lds(block_size);
 
-    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, c8, fm, ctl);
+    k_blk_init<<<vgrid, kThreads, 0, st>>>(n, colors_out, c8, hp, fm, ctl);
     BLK_CHECK(hipGetLastError());
     long long k = 0;
     int batch = 4;
@@ -600,7 +618,7 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
         for (long long j = 0; j < nb; ++j) {
             ++k;
             k_blk_first<<<bgrid, kThreads, lds_bytes, st>>>(n, block_size, nblocks, row_ptr, col_idx, colors_out,
-                                                            c8, fm, tent, t8);
+                                                            c8, fm, hp, tent, t8);
             k_blk_check<<<cgrid, kThreads, 0, st>>>(n, (int)k, row_ptr, col_idx, priority, colors_out, tent, t8, c8,
                                                   fm, ctl);
             BLK_CHECK(hipGetLastError());
