@@ -27,12 +27,12 @@
 // earlier in its block (hp: uint8[n], decided by the first walk of its row)
 // and the mask of its neighbours' committed colours 1..64 (fm: uint64[n]).
 // Phase 1 takes the committed colours from fm and walks a row only for the
-// neighbours inside the block, and only while hp is set;
-// a vertex with 1..64 all taken scans its row with the int32 colours.
-// Phase 2 gathers the bytes: equal bytes are equal colours unless both
-// sides are 255 or more (then tent decides).
-// Block sizes run from 1 to kMaxBlock (LDS per wavefront of phase 1: 4 bytes
-// per vertex of its block plus the state of one 64-vertex chunk).
+// neighbours inside the block, and only while hp is set; a vertex with 1..64
+// all taken scans its row with the int32 colours.  Phase 2 gathers the
+// bytes: equal bytes are equal colours unless both sides are 255 or more
+// (then tent decides).  Block sizes run from 1 to kMaxBlock (LDS per
+// wavefront of phase 1: 4 bytes and 1 bit per vertex of its block plus the
+// state of one 64-vertex chunk).
 //
 // Both row passes work on chunks of 64 consecutive vertices: a wavefront
 // compacts the chunk's vertices of U, prefix-sums their degrees and walks
