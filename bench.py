@@ -218,11 +218,14 @@ def bench_blocks(args):
     ms_per_step = 1000.0 * wall / args.steps
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     log("timed %d steps: %.3f ms/step (wall), %.3f ms/step (events)" % (args.steps, ms_per_step, ev_ms))
-    # algorithmic bytes of one colouring: per round, both row passes read
-    # neighbour id + colour (8 B) per entry of an uncoloured row and each
-    # reads the row_ptr pair and colour of every vertex of its chunks
-    # (2 x 12 B per vertex); the commits write each colour once (without
-    # priorities phase 2 gathers only for the smaller ids: counted in full)
+    # yardstick bytes of one colouring, fixed by the input and the rounds: a
+    # plain two-pass round reads neighbour id + colour (8 B) per entry of an
+    # uncoloured row in each pass and the row_ptr pair and colour of every
+    # vertex (2 x 12 B), and the commits write each colour once.  The kernels
+    # move less (phase 1 takes committed colours from per-vertex masks and
+    # walks only rows with an in-block predecessor; phase 2 gathers one byte
+    # per preceding entry until the vertex loses), so achieved/peak is
+    # against the plain method's traffic.
     algo = 16 * st.edge_work + 24 * g.n * st.rounds + 4 * g.n
     achieved = algo / (ev_ms / 1e3) / 1e9
     roofline = {"kernel": "whole call (k_blk_first + k_blk_check)", "bound": "hbm",
