@@ -66,7 +66,7 @@ def _load():
     lib.or_dataflow.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, i32p]
     lib.or_dataflow.restype = ctypes.c_int32
     lib.or_block_gs.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, i32p, i64p,
-                                ctypes.c_int32, ctypes.c_int32]
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.or_block_gs.restype = ctypes.c_int32
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
@@ -158,11 +158,12 @@ class BlockResult(NamedTuple):
 
 
 def block_gs(row_ptr, col_idx, key: Optional[np.ndarray] = None, block: int = 64,
-             max_rounds: Optional[int] = None) -> BlockResult:
+             max_rounds: Optional[int] = None, threads: int = 1) -> BlockResult:
     """Block Gauss-Seidel speculative colouring: Algorithm 2 in rounds where
     each block of `block` consecutive ids colours its worklist vertices in id
     order, seeing the block's own colours of the round; conflicts by (key,
-    id) precedence as in Algorithm 2."""
+    id) precedence as in Algorithm 2.  threads: OpenMP threads (0 = all);
+    the result does not depend on it."""
     row_ptr, col_idx = _csr_args(row_ptr, col_idx)
     n = row_ptr.shape[0] - 1
     if key is not None:
@@ -174,7 +175,7 @@ def block_gs(row_ptr, col_idx, key: Optional[np.ndarray] = None, block: int = 64
     log = np.zeros((max_log, 4), dtype=np.int64)
     k = _load().or_block_gs(n, _p(row_ptr, ctypes.c_int32), _p(col_idx, ctypes.c_int32),
                             _p(key, ctypes.c_uint32), int(block), _p(color, ctypes.c_int32),
-                            _p(log, ctypes.c_int64), max_log, max_rounds)
+                            _p(log, ctypes.c_int64), max_log, max_rounds, int(threads))
     if k == -1:
         raise ValueError("block size must be at least 1")
     if k < 0:

@@ -17,6 +17,13 @@ Features of vertex v (d = degree, N(v) its neighbours):
   7          h-index of the neighbour degrees: largest h such that at least
              h neighbours have degree >= h
 MLP: x = (log1p(f) - mean) / std, y = W3 relu(W2 relu(W1 x + b1) + b2) + b3.
+Normalisation: mean and population standard deviation of log1p(f) per
+feature over the training vertices (variance floored at 1e-12).
+Training target of smallest-last position r among n vertices:
+log(1 + r) / log(max(n, 2)).
+Optimiser: one Adam step (Kingma and Ba, "Adam: a method for stochastic
+optimization", 2015, Algorithm 1) with bias-corrected first and second
+moment estimates.
 """
 from __future__ import annotations
 
@@ -171,3 +178,40 @@ def keys_from_scores(s):
     non-negative: sign bit set)."""
     u = np.asarray(s, dtype=np.float32).view(np.uint32)
     return np.where(u & np.uint32(0x80000000), ~u, u | np.uint32(0x80000000)).astype(np.uint32)
+
+
+def feature_sums(F):
+    """Per feature: sum of log1p(f) and sum of log1p(f)^2 over the rows of F
+    (the statistics the normalisation is fitted from)."""
+    L = np.log1p(np.asarray(F, dtype=np.float64))
+    return np.concatenate([L.sum(axis=0), (L * L).sum(axis=0)])
+
+
+def norm_from_sums(sums, count):
+    """Mean and population standard deviation per feature from the sums of
+    feature_sums over `count` vertices; the variance is floored at 1e-12."""
+    sums = np.asarray(sums, dtype=np.float64)
+    mean = sums[:NF] / count
+    var = np.maximum(sums[NF:] / count - mean * mean, 1e-12)
+    return np.concatenate([mean, np.sqrt(var)])
+
+
+def rank_target(rank):
+    """Target of smallest-last position r (0 = coloured first) among n
+    vertices: log(1 + r) / log(max(n, 2))."""
+    rank = np.asarray(rank, dtype=np.float64)
+    n = rank.shape[0]
+    return np.log1p(rank) / np.log(max(n, 2))
+
+
+def adam_step(w, m, v, g, step, lr, beta1, beta2, eps):
+    """One Adam step on parameters w with first / second moment estimates m, v
+    and gradient g (all float64; step >= 1 counts this step).  Returns the
+    new (w, m, v)."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

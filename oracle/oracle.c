@@ -326,20 +326,22 @@ int or_num_threads(void) { return omp_get_max_threads(); }
  * independent within phase 1, so their order of visit does not matter.
  * log (may be NULL) receives per round: k, |U_k|, sum of degrees over U_k,
  * number of losers; at most max_log rounds.
+ * nthreads <= 0 means OpenMP's default; the result never depends on it.
  * Returns the number of rounds, or -5 when max_rounds is exceeded.
  */
 int32_t or_block_gs(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* key,
-                    int32_t block, int32_t* color, int64_t* log, int32_t max_log, int32_t max_rounds) {
+                    int32_t block, int32_t* color, int64_t* log, int32_t max_log, int32_t max_rounds,
+                    int32_t nthreads) {
     if (block < 1) return -1;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
     const int32_t dmax = or_max_degree(n, row_ptr);
     const size_t nn = (size_t)(n > 0 ? n : 1);
     int32_t* S = (int32_t*)malloc(sizeof(int32_t) * nn);
     int32_t* tent = (int32_t*)malloc(sizeof(int32_t) * nn);
     unsigned char* inU = (unsigned char*)malloc(nn);
     unsigned char* lose = (unsigned char*)malloc(nn);
-    int64_t* forbidden = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax + 2));
-    for (int32_t c = 0; c < dmax + 2; ++c) forbidden[c] = -1;
     for (int32_t v = 0; v < n; ++v) color[v] = 0;
+    const int64_t nblocks = ((int64_t)n + block - 1) / block;
     int64_t nU = n;
     int32_t k = 0;
     while (nU > 0) {
@@ -348,26 +350,38 @@ int32_t or_block_gs(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, c
         memcpy(S, color, sizeof(int32_t) * (size_t)n);
         for (int32_t v = 0; v < n; ++v) inU[v] = color[v] == 0;
 
-        /* Phase 1: blocks in turn, each block's worklist vertices in id order. */
-        for (int64_t b0 = 0; b0 < n; b0 += block) {
-            const int64_t b1 = b0 + block < n ? b0 + block : n;
-            for (int64_t vv = b0; vv < b1; ++vv) {
-                const int32_t v = (int32_t)vv;
-                if (!inU[v]) continue;
-                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-                    const int32_t w = col_idx[e];
-                    if (w == v) continue;
-                    forbidden[S[w]] = v;
-                    if (inU[w] && w >= b0 && w < v) forbidden[tent[w]] = v;
+        /* Phase 1: each block's worklist vertices in id order.  Blocks read
+         * only S and their own tent entries, so they are independent and run
+         * on the threads in any order; each thread stamps a forbidden array
+         * of its own, fresh every round, with the visited vertex. */
+#pragma omp parallel num_threads(nthreads)
+        {
+            int64_t* forbidden = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax + 2));
+            for (int32_t c = 0; c < dmax + 2; ++c) forbidden[c] = -1;
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t b = 0; b < nblocks; ++b) {
+                const int64_t b0 = b * block;
+                const int64_t b1 = b0 + block < n ? b0 + block : n;
+                for (int64_t vv = b0; vv < b1; ++vv) {
+                    const int32_t v = (int32_t)vv;
+                    if (!inU[v]) continue;
+                    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                        const int32_t w = col_idx[e];
+                        if (w == v) continue;
+                        forbidden[S[w]] = v;
+                        if (inU[w] && w >= b0 && w < v) forbidden[tent[w]] = v;
+                    }
+                    int32_t c = 1;
+                    while (forbidden[c] == v) ++c;
+                    tent[v] = c;
                 }
-                int32_t c = 1;
-                while (forbidden[c] == v) ++c;
-                tent[v] = c;
             }
+            free(forbidden);
         }
 
         /* Phase 2: conflicts against every neighbour's colour of this round. */
         int64_t work = 0, nR = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1024) reduction(+ : work)
         for (int32_t v = 0; v < n; ++v) {
             if (!inU[v]) continue;
             unsigned char l = 0;
@@ -397,6 +411,6 @@ int32_t or_block_gs(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, c
     free(tent);
     free(inU);
     free(lose);
-    free(forbidden);
     return k;
 }
+

@@ -135,3 +135,60 @@ def test_library_host_smallest_last_matches_oracle():
         r, d = L.smallest_last_rank(g.row_ptr, g.col_idx)
         ro, do = oracle.smallest_last_rank(g.row_ptr, g.col_idx)
         assert np.array_equal(r, ro) and d == do
+
+
+def test_adam_two_steps_by_hand():
+    """Adam with beta1 = 1/2, beta2 = 3/4, lr = 1, eps = 0 from zero moments,
+    worked out by hand: gradient 2 gives m = 1, v = 1, bias-corrected 2 and
+    4, a step of 2 / 2 = 1; then gradient -2 gives m = 1/2 - 1 = -1/2,
+    v = 3/4 + 1 = 7/4, corrected -1/2 / (3/4) = -2/3 and (7/4) / (7/16) = 4,
+    a step of (-2/3) / 2 = -1/3."""
+    w, m, v = OL.adam_step(np.array([5.0]), np.zeros(1), np.zeros(1), np.array([2.0]), 1, 1.0, 0.5, 0.75, 0.0)
+    assert np.allclose([w[0], m[0], v[0]], [4.0, 1.0, 1.0], rtol=1e-15)
+    w, m, v = OL.adam_step(w, m, v, np.array([-2.0]), 2, 1.0, 0.5, 0.75, 0.0)
+    assert np.allclose([w[0], m[0], v[0]], [4.0 + 1.0 / 3.0, -0.5, 1.75], rtol=1e-15)
+
+
+def test_adam_constant_gradient_moves_by_lr():
+    """With a constant gradient g the bias-corrected moments are g and g^2 at
+    every step, so each step moves every parameter by lr * g / (|g| + eps)
+    (= lr * sign(g) for eps = 0), independent of the betas."""
+    g = np.array([3.0, -0.25, 1e-3, -7.0])
+    w = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    for step in range(1, 6):
+        w, m, v = OL.adam_step(w, m, v, g, step, 0.01, 0.9, 0.999, 0.0)
+        assert np.allclose(w, -0.01 * step * np.sign(g), rtol=1e-12, atol=1e-15)
+    # zero gradient with zero moments: no move (0 / (0 + eps))
+    w2, _, _ = OL.adam_step(np.ones(3), np.zeros(3), np.zeros(3), np.zeros(3), 1, 0.1, 0.9, 0.999, 1e-8)
+    assert np.array_equal(w2, np.ones(3))
+
+
+def test_normalisation_closed_forms():
+    """Feature e - 1 (log1p = 1) on every vertex: mean 1, spread 0 (floored
+    at 1e-6); features e^a - 1 and e^b - 1 on half the vertices each: mean
+    (a + b) / 2, standard deviation |a - b| / 2."""
+    n = 10
+    F = np.zeros((n, OL.NF))
+    F[:, 0] = np.e - 1.0
+    F[:5, 1] = np.expm1(1.0)
+    F[5:, 1] = np.expm1(3.0)
+    F[:, 2] = 0.0
+    norm = OL.norm_from_sums(OL.feature_sums(F), n)
+    assert abs(norm[0] - 1.0) < 1e-12 and abs(norm[OL.NF] - 1e-6) < 1e-12
+    assert abs(norm[1] - 2.0) < 1e-12 and abs(norm[OL.NF + 1] - 1.0) < 1e-9
+    assert norm[2] == 0.0 and abs(norm[OL.NF + 2] - 1e-6) < 1e-12
+    # sums over parts add up: the statistics of a union are the sums of the parts
+    s = OL.feature_sums(F[:3]) + OL.feature_sums(F[3:])
+    assert np.allclose(s, OL.feature_sums(F), rtol=1e-14)
+
+
+def test_rank_target_closed_forms():
+    """Position 0 maps to 0, position n - 1 to log(n) / log(n) = 1, and
+    position sqrt(n) - 1 to 1/2; the map is strictly increasing."""
+    n = 1024
+    t = OL.rank_target(np.arange(n))
+    assert t[0] == 0.0 and abs(t[n - 1] - 1.0) < 1e-15 and abs(t[31] - 0.5) < 1e-15
+    assert np.all(np.diff(t) > 0)
+    assert np.array_equal(OL.rank_target(np.zeros(1)), [0.0])

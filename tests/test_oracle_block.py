@@ -153,3 +153,37 @@ def test_self_loops_and_duplicates_are_harmless():
         a = oracle.block_gs(g.row_ptr, g.col_idx, None, block)
         b = oracle.block_gs(rp, ci, None, block)
         assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+
+
+@pytest.mark.parametrize("block", [1, 5, 64, 1000])
+@pytest.mark.parametrize("order", ["natural", "perm", "ties"])
+def test_result_independent_of_threads(block, order):
+    """Phase 1 runs the blocks on OpenMP threads and phase 2 the vertices:
+    colours, rounds and the per-round log are those of one thread at every
+    thread count."""
+    g = graphgen.rmat(15, 8, (0.55, 0.1, 0.1), 5)
+    key = {"natural": None, "perm": graphgen.random_priority(g.n, 6),
+           "ties": graphgen.random_keys(g.n, 7, bits=3)}[order]
+    ref = oracle.block_gs(g.row_ptr, g.col_idx, key, block, threads=1)
+    for th in (2, 3, 8, 0):
+        r = oracle.block_gs(g.row_ptr, g.col_idx, key, block, threads=th)
+        assert np.array_equal(r.colors, ref.colors) and r.rounds == ref.rounds
+        assert np.array_equal(r.log, ref.log)
+
+
+def test_stamps_do_not_leak_between_rounds():
+    """A vertex that lost keeps no forbidden colour from its earlier visit: on
+    these graphs (random keys with ties, small blocks) the oracle equals the
+    set definition, which rebuilds every forbidden set from scratch."""
+    rng = np.random.default_rng(42)
+    for _ in range(400):
+        n = int(rng.integers(4, 22))
+        p = rng.uniform(0.15, 0.6)
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+        adj = oracle.edges_to_adj(n, edges)
+        rp, ci = oracle.adj_to_csr(adj)
+        key = rng.integers(0, 3, n).astype(np.uint32)
+        block = int(rng.integers(2, 7))
+        r = oracle.block_gs(rp, ci, key, block=block, threads=2)
+        c, k = oracle.block_gs_py(adj, key, block=block)
+        assert list(r.colors) == list(c) and r.rounds == k
