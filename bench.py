@@ -112,61 +112,96 @@ def load_traffic_file(workload, order):
 
 
 def load_traffic(workload, order, kernel, launches):
-    """HBM bytes per launch of one kernel measured by rocprofv3 counters, if
-    they were taken on the current kernel sources; else None."""
+    """Bytes per launch of one kernel between L2 and the memory fabric,
+    measured by rocprofv3 counters, if they were taken on the current kernel
+    sources; else None."""
     d = load_traffic_file(workload, order)
     k = (d or {}).get("kernels", {}).get(kernel)
     if not k:
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k.get("l2_fabric_bytes_per_launch")
 
 
-def derive_traffic(fetch_csv, write_csv, workload, order, steps_colourings, out_path=None):
-    """Write profiles/traffic_<workload>_<order>.json from two rocprofv3 --pmc
-    runs of this script (FETCH_SIZE, then WRITE_SIZE, both with
-    --copy-calibration).  Each counter is scaled by what it reads for the
-    1 GiB device copy of the calibration (bytes known), per kernel launch."""
+# rocprofv3 --pmc passes of the traffic measurement (at most 4 TCC counters
+# each): read requests by size, write requests by size, L2 hits and misses
+TRAFFIC_PASSES = (
+    ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum"),
+    ("TCC_EA0_WRREQ_64B_sum", "TCC_EA0_WRREQ_sum", "TCC_BUBBLE_sum"),
+    ("TCC_HIT_sum", "TCC_MISS_sum"),
+)
+
+
+def derive_traffic(csv_paths, workload, order, out_path=None):
+    """Write profiles/traffic_<workload>_<order>.json from the rocprofv3
+    --pmc runs of TRAFFIC_PASSES (each run: this script with --steps 1
+    --warmup 0 --copy-calibration).  Read bytes are summed by request size
+    (32, 64 and 128 bytes), write bytes likewise (64-byte requests and the
+    rest at 32); both are counted where the L2 meets the memory fabric, so
+    reads the Infinity Cache serves are included (the counters cannot tell
+    them apart).  The 1 GiB device copy of the calibration checks the byte
+    arithmetic: it must read and write 1 GiB."""
     import csv
     import re
 
-    def per_kernel(path, counter):
-        # per round kernel: total and dispatches; every library kernel
-        # (k_zero_ctl runs once per colouring): total and colourings
-        tot, disp, copy, lib, calls = {}, {}, None, 0.0, 0
+    tot, disp = {}, {}        # (kernel, counter) -> sum over dispatches, dispatches
+    lib, calls = {}, {}       # counter -> sum over every library kernel; colourings
+    copy = {}
+
+    for path in csv_paths:
         for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
-                continue
-            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            cn, name, val = r["Counter_Name"], r["Kernel_Name"], float(r["Counter_Value"])
             if "copyBuffer" in name and int(r["Grid_Size"]) == 131072:
-                copy = val  # the 1 GiB calibration copy
+                copy[cn] = val  # the 1 GiB calibration copy
                 continue
             if re.search(r"::k_\w+", name):
-                lib += val
-                calls += "k_zero_ctl" in name
-            m = re.search(r"k_(inc_[abc]|phase[12]|flow|batch)\b", name)
+                lib[cn] = lib.get(cn, 0.0) + val
+                calls[cn] = calls.get(cn, 0) + ("k_zero_ctl" in name)
+            m = re.search(r"k_(inc_[ac]|phase[12]|flow|batch)\b", name)
             if m:
-                key = m.group(1)
+                key = (m.group(1), cn)
                 tot[key] = tot.get(key, 0.0) + val
                 disp[key] = disp.get(key, 0) + 1
-        return tot, disp, copy, lib, calls
 
-    ft, fd, fcopy, flib, fcalls = per_kernel(fetch_csv, "FETCH_SIZE")
-    wt, wd, wcopy, wlib, wcalls = per_kernel(write_csv, "WRITE_SIZE")
-    gib_kib = 1024.0 * 1024.0
-    fscale = gib_kib / fcopy if fcopy else None   # true read bytes / counted
-    wscale = gib_kib / wcopy if wcopy else None
+    def rd_bytes(get):
+        return 32 * get("TCC_EA0_RDREQ_32B_sum") + 64 * get("TCC_EA0_RDREQ_64B_sum") + \
+            128 * get("TCC_EA0_RDREQ_128B_sum")
+
+    def wr_bytes(get):
+        w64 = get("TCC_EA0_WRREQ_64B_sum")
+        return 64 * w64 + 32 * (get("TCC_EA0_WRREQ_sum") - w64)
+
+    def fetch_size(get):
+        # rocprofv3's derived FETCH_SIZE expression (bytes), for comparison
+        b, rq, r32 = get("TCC_BUBBLE_sum"), get("TCC_EA0_RDREQ_sum"), get("TCC_EA0_RDREQ_32B_sum")
+        return 128 * b + 64 * (rq - b - r32) + 32 * r32
+
     out = {"kernel_source_sha256": kernel_source_digest(workload), "workload": workload, "order": order,
-           "copy_calibration_kib": {"FETCH_SIZE": fcopy, "WRITE_SIZE": wcopy, "true_kib": gib_kib},
-           "scale": {"FETCH_SIZE": fscale, "WRITE_SIZE": wscale}, "kernels": {}}
-    if fcalls and wcalls:
-        rd, wr = flib / fcalls * 1024.0 * fscale, wlib / wcalls * 1024.0 * wscale
-        out["per_colouring"] = {"colourings_counted": fcalls, "read_bytes": rd, "write_bytes": wr,
-                                "hbm_bytes": rd + wr}
-    for k in sorted(ft):
-        rd = ft[k] / fd[k] * 1024.0 * fscale
-        wr = wt.get(k, 0.0) / max(wd.get(k, 1), 1) * 1024.0 * wscale
-        out["kernels"][k] = {"launches_counted": fd[k], "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
-                             "hbm_bytes_per_launch": rd + wr}
+           "method": "read bytes = 32 x TCC_EA0_RDREQ_32B + 64 x TCC_EA0_RDREQ_64B + 128 x TCC_EA0_RDREQ_128B; "
+                     "write bytes = 64 x TCC_EA0_WRREQ_64B + 32 x (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B); "
+                     "counted between L2 and the memory fabric (Infinity Cache hits included)",
+           "passes": [list(p) for p in TRAFFIC_PASSES], "kernels": {}}
+    if copy:
+        g = lambda c: copy.get(c, 0.0)
+        out["copy_check"] = {"true_bytes": 1 << 30, "read_bytes": rd_bytes(g), "write_bytes": wr_bytes(g),
+                             "fetch_size_formula_bytes": fetch_size(g),
+                             "read_requests": {c: g(c) for c in TRAFFIC_PASSES[0]}}
+    ncol = max(calls.get("TCC_EA0_RDREQ_sum", 0), 1)
+    gl = lambda c: lib.get(c, 0.0) / max(calls.get(c, 0), 1)
+    rd, wr = rd_bytes(gl), wr_bytes(gl)
+    out["per_colouring"] = {"colourings_counted": ncol, "read_bytes": rd, "write_bytes": wr,
+                            "l2_fabric_bytes": rd + wr}
+    for k in sorted({k for k, _ in tot}):
+        g = lambda c: tot.get((k, c), 0.0) / max(disp.get((k, c), 0), 1)
+        rdk, wrk = rd_bytes(g), wr_bytes(g)
+        hit, miss = g("TCC_HIT_sum"), g("TCC_MISS_sum")
+        out["kernels"][k] = {
+            "launches_counted": disp.get((k, "TCC_EA0_RDREQ_sum"), 0),
+            "read_bytes_per_launch": rdk, "write_bytes_per_launch": wrk,
+            "l2_fabric_bytes_per_launch": rdk + wrk,
+            "fetch_size_formula_bytes_per_launch": fetch_size(g),
+            "read_requests_per_launch": {c.replace("TCC_EA0_RDREQ_", "").replace("_sum", ""): g(c)
+                                         for c in TRAFFIC_PASSES[0]},
+            "l2_hit_rate": hit / (hit + miss) if hit + miss else None}
     path = out_path or os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, order))
     json.dump(out, open(path, "w"), indent=1, sort_keys=True)
     print(path)
@@ -218,32 +253,35 @@ def bench_blocks(args):
     ms_per_step = 1000.0 * wall / args.steps
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     log("timed %d steps: %.3f ms/step (wall), %.3f ms/step (events)" % (args.steps, ms_per_step, ev_ms))
-    # yardstick bytes of one colouring, fixed by the input and the rounds: a
-    # plain two-pass round reads neighbour id + colour (8 B) per entry of an
-    # uncoloured row in each pass and the row_ptr pair and colour of every
-    # vertex (2 x 12 B), and the commits write each colour once.  The kernels
-    # move less (phase 1 takes committed colours from per-vertex masks and
-    # walks only rows with an in-block predecessor; phase 2 gathers one byte
-    # per preceding entry until the vertex loses), so achieved/peak is
-    # against the plain method's traffic.
-    algo = 16 * st.edge_work + 24 * g.n * st.rounds + 4 * g.n
-    achieved = algo / (ev_ms / 1e3) / 1e9
+    # roofline over the whole call against the input's floor: read every row
+    # once (4 B per entry) and write every colour (plus the row_ptr, 4 B per
+    # vertex).  The plain two-pass method's bytes (8 B per entry of an
+    # uncoloured row in each pass, 24 B per vertex and round, one colour
+    # write) are reported beside it as an effective rate only: the kernels
+    # move less than that.
+    bmin = 4 * g.nnz + 8 * g.n
+    plain = 16 * st.edge_work + 24 * g.n * st.rounds + 4 * g.n
+    achieved = bmin / (ev_ms / 1e3) / 1e9
     roofline = {"kernel": "whole call (k_blk_first + k_blk_check)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_step": int(algo)}
-    # the block oracle (one core) on the same workload: baseline and parity;
-    # the serial greedy for the colour count
+                "bytes_model": "lower bound: 4 B per row entry + 8 B per vertex",
+                "algorithmic_bytes_per_step": int(bmin),
+                "effective": {"plain_method_bytes": int(plain),
+                              "plain_method_GBps": round(plain / (ev_ms / 1e3) / 1e9, 1),
+                              "plain_method_frac": round(plain / (ev_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    # the block oracle (every host thread) on the same workload: baseline
+    # and parity; the serial greedy for the colour count
     cpu = None
     parity = None
     greedy_colors = None
     if not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
-        ref = oracle.block_gs(g.row_ptr, g.col_idx, key, B)
+        ref = oracle.block_gs(g.row_ptr, g.col_idx, key, B, threads=0)
         dt = time.perf_counter() - t
         parity = bool(np.array_equal(ref.colors, out.cpu().numpy())) and ref.rounds == st.rounds
-        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": oracle.num_threads(), "kind": "oracle",
                "sample": "the full workload (%.1f s)" % dt}
         greedy_colors = int(oracle.greedy(g.row_ptr, g.col_idx, key).max())
         log("block oracle %.1fs parity=%s; serial greedy %d colours" % (dt, parity, greedy_colors))
@@ -266,8 +304,8 @@ def bench_blocks(args):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--derive-traffic":
-        # --derive-traffic FETCH_CSV WRITE_CSV WORKLOAD ORDER
-        derive_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], None)
+        # --derive-traffic WORKLOAD ORDER CSV [CSV ...] (one per pass of TRAFFIC_PASSES)
+        derive_traffic(sys.argv[4:], sys.argv[2], sys.argv[3])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,9 +462,10 @@ def main():
         achieved = (algo[dom] / max(launches, 1)) / (kern[dom]["avg_us"] * 1e-6) / 1e9
         traffic = load_traffic(args.workload, args.order, dom, launches)
         if traffic is not None:
-            traffic = {"hbm_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch":
+            traffic = {"l2_fabric_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch":
                        round(algo[dom] / max(launches, 1)),
-                       "GB_per_s": round(traffic / (kern[dom]["avg_us"] * 1e-6) / 1e9, 1)}
+                       "GB_per_s": round(traffic / (kern[dom]["avg_us"] * 1e-6) / 1e9, 1),
+                       "counted": "between L2 and the memory fabric, Infinity Cache hits included"}
         roofline = {
             "kernel": dom,
             "bound": "hbm",
@@ -447,10 +486,12 @@ def main():
         whole = (load_traffic_file(args.workload, args.order) or {}).get("per_colouring")
         if whole:
             # counter bytes of every library kernel of one colouring over the
-            # step time (the measured-traffic share of HBM peak)
+            # step time: traffic between L2 and the fabric, an upper bound of
+            # the HBM share (Infinity Cache hits are counted too)
             roofline["whole_call_traffic"] = {
-                "hbm_bytes": int(whole["hbm_bytes"]), "GBps": round(whole["hbm_bytes"] / step_s / 1e9, 1),
-                "frac": round(whole["hbm_bytes"] / step_s / 1e9 / HBM_PEAK_GBS, 4)}
+                "l2_fabric_bytes": int(whole["l2_fabric_bytes"]),
+                "GBps": round(whole["l2_fabric_bytes"] / step_s / 1e9, 1),
+                "frac_upper_bound": round(whole["l2_fabric_bytes"] / step_s / 1e9 / HBM_PEAK_GBS, 4)}
         roofline["effective"] = {
             "plain_method_bytes": int(b_plain), "plain_method_GBps": round(b_plain / step_s / 1e9, 1),
             "plain_method_frac": round(b_plain / step_s / 1e9 / HBM_PEAK_GBS, 4),
@@ -619,8 +660,9 @@ def bench_batch(args):
     bmin = 4 * nnz + 8 * V  # read every row once, write every colour
     traffic = load_traffic(args.workload, "natural", "batch", 1)
     if traffic is not None:
-        traffic = {"hbm_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch": bmin,
-                   "GB_per_s": round(traffic / (kms / 1000.0) / 1e9, 1)}
+        traffic = {"l2_fabric_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch": bmin,
+                   "GB_per_s": round(traffic / (kms / 1000.0) / 1e9, 1),
+                   "counted": "between L2 and the memory fabric, Infinity Cache hits included"}
     res = {
         "metric": "edges colored/sec, batched small graphs (one persistent launch)",
         "value": round(edges / (ms / 1000.0), 1), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,

@@ -41,9 +41,11 @@
  * names a code.  A HIP error raised by an earlier, unrelated call on the same
  * device may surface here as GCOLOR_EHIP.
  *
- * Streams: all device work is enqueued on `stream` (0 = the null stream).  The
- * colouring entry points read small counters back to the host to decide when
- * the worklist is empty, so they return only after the colouring is complete.
+ * Streams: all device work is enqueued on `stream` (0 = the null stream).
+ * color_graph, color_graph_ex and color_graph_blocks read small counters back
+ * to the host to decide when the worklist is empty, so they return only after
+ * the colouring is complete; color_graph_async (a round budget instead) and
+ * color_graph_batch never wait on the host.
  */
 #ifndef GCOLOR_H
 #define GCOLOR_H
@@ -74,7 +76,7 @@ enum {
     GCOLOR_STATS = 1u << 1,    /* fill *stats (rounds, colours, edge work) */
     GCOLOR_PLAIN = 1u << 2,    /* use the plain engine: every round rescans every worklist row
                                   (same result as the default incremental engine) */
-    GCOLOR_DATAFLOW = 1u << 3  /* a different colouring: the dataflow algorithm (section "A
+    GCOLOR_DATAFLOW = 1u << 3, /* a different colouring: the dataflow algorithm (section "A
                                   dataflow algorithm", Algorithm 3) in rounds.  A vertex is
                                   coloured once all of its preceding neighbours are, with the
                                   smallest colour none of them holds; the result is the serial
@@ -83,6 +85,13 @@ enum {
                                   vertices on the longest path along which each vertex precedes
                                   the next (n on a path in natural order).  Not combinable with
                                   GCOLOR_PLAIN. */
+    GCOLOR_SERIAL_TAIL = 1u << 4 /* a different colouring: the rounds run while more than
+                                    gcolor_get_serial_tail() vertices are uncoloured, then the
+                                    rest are coloured one at a time in ascending (priority, id)
+                                    order, each with the smallest colour none of its neighbours
+                                    holds (the switch to a sequential computation that section
+                                    "Iterative and degree of concurrency" suggests once
+                                    conflicts are few).  Default engine only. */
 };
 
 typedef struct gcolor_stats {
@@ -91,7 +100,7 @@ typedef struct gcolor_stats {
     int64_t edge_work;  /* sum over rounds of the degrees of the worklist (the first 65536
                            rounds: the device keeps per-round records for those) */
     int32_t status;     /* 0, or the code the call returned */
-    int32_t reserved;
+    int32_t serial_tail; /* vertices coloured by the sequential finish (GCOLOR_SERIAL_TAIL) */
 } gcolor_stats_t;
 
 /* Per-round record written to round_log (host memory) by color_graph_ex:
@@ -139,6 +148,39 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                    gcolor_round_t* round_log, int32_t max_log, gcolor_stream_t stream);
 
 /*
+ * Stream-ordered colouring (Algorithm 2's loop "while U is not empty" run
+ * for a fixed budget of rounds, so that the host never waits): every kernel
+ * is enqueued on `stream` and the call returns at once, with no host
+ * synchronisation and no allocation, so it may be captured into a HIP graph
+ * and replayed.  The colouring is color_graph's, vertex for vertex (the
+ * default incremental engine).
+ *   n, row_ptr, col_idx, priority, colors_out: as color_graph;
+ *   nnz        row_ptr[n] (the caller knows it; nothing is read back);
+ *   workspace  device memory of gcolor_workspace_bytes(n, nnz) bytes, owned
+ *              by the caller (required);
+ *   max_rounds the round budget (>= 1): exactly this many rounds are
+ *              enqueued; rounds after the worklist has emptied find no work
+ *              and return at once (a few microseconds each);
+ *   flags      0 or GCOLOR_VALIDATE (the CSR checks run on the device: a
+ *              malformed CSR stops the colouring before any row is walked);
+ *   stats_dev  device gcolor_stats_t, written when the stream reaches the
+ *              end of the call: rounds, colours and edge work as
+ *              color_graph_ex reports them, and status = GCOLOR_OK,
+ *              GCOLOR_ECSR (validation failed), GCOLOR_EROUNDS (the budget
+ *              ended with vertices uncoloured; colors_out is then
+ *              incomplete) or GCOLOR_EINTERNAL.  The other fields are 0
+ *              unless status is GCOLOR_OK.
+ * The return value reports only what the host can see: GCOLOR_EINVAL
+ * (negative n or nnz, nnz >= 2^31, max_rounds < 1, NULL pointers, other
+ * flags), GCOLOR_EWORKSPACE, GCOLOR_EHIP (a launch failed).  The process-wide
+ * round cap does not apply (the budget replaces it).  Calls sharing one
+ * workspace must not overlap.
+ */
+int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      const uint32_t* priority, int32_t* colors_out, void* workspace, size_t ws_bytes,
+                      int32_t max_rounds, uint32_t flags, gcolor_stats_t* stats_dev, gcolor_stream_t stream);
+
+/*
  * Tuning (process-wide, applies to later calls): bin_limits[4] are the
  * largest degrees of bins 0..3 (one lane, 4 lanes, 16 lanes and one
  * wavefront per vertex); larger degrees take a workgroup per vertex.  Must be
@@ -151,15 +193,15 @@ int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu);
 int gcolor_get_tuning(int32_t* bin_limits, int32_t* blocks_per_cu);
 
 /*
- * Blocks per CU of the incremental engine's round kernels: blocks_a for the
- * dirty-vertex kernel, blocks_c for the commit kernel (which also completes
- * the counters of dirty vertices with dirty preceding neighbours); blocks_b
- * is checked and stored but no kernel uses it.  1..64 each, 0 = the common
- * blocks_per_cu above (the default).  Errors: GCOLOR_EINVAL outside 0..64.
- * Results never depend on it.
+ * Blocks per CU of the incremental engine's two round kernels: blocks_a for
+ * the dirty-vertex kernel, blocks_c for the commit kernel (which also
+ * completes the counters of dirty vertices with dirty preceding
+ * neighbours).  1..64 each, 0 = the common blocks_per_cu above (the
+ * default).  Errors: GCOLOR_EINVAL outside 0..64.  Results never depend on
+ * it.
  */
-int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_b, int32_t blocks_c);
-int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* blocks_c);
+int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_c);
+int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_c);
 
 /*
  * Round cap (process-wide, applies to later color_graph / color_graph_ex
@@ -175,6 +217,15 @@ int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* bloc
  */
 int gcolor_set_round_cap(int32_t max_rounds);
 int gcolor_get_round_cap(int32_t* max_rounds);
+
+/*
+ * Size of the sequential finish of GCOLOR_SERIAL_TAIL (process-wide, applies
+ * to later calls): the rounds stop once at most max_vertices vertices are
+ * uncoloured.  1..8192 (one workgroup sorts and colours them); default 1024.
+ * Errors: GCOLOR_EINVAL outside 1..8192 or a NULL pointer.
+ */
+int gcolor_set_serial_tail(int32_t max_vertices);
+int gcolor_get_serial_tail(int32_t* max_vertices);
 
 /*
  * Block Gauss-Seidel variant of the speculative colouring (Algorithm 2 run
@@ -228,9 +279,9 @@ int gcolor_get_batch_tuning(int32_t* block_threads, int32_t* lds_factor, int32_t
  * milliseconds and launch count of a kernel: 0 = plain phase 1 (tentative
  * colouring), 1 = plain phase 2 (conflict detection and worklist
  * compaction), 2 = incremental tentative colours of dirty vertices,
- * 3 = (no kernel: the incremental counters are completed in 4),
- * 4 = incremental counter completion, commit and push,
- * 5 = dataflow round.
+ * 3 = incremental dirty lists built from the round's bitmap (two kernels
+ * per round, timed together), 4 = incremental counter completion, commit
+ * and dirty marks, 5 = dataflow round.
  */
 int gcolor_profile(int32_t enable);
 int gcolor_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
@@ -292,18 +343,30 @@ int gcolor_wall_clock_khz(int32_t* khz);
  * triangle estimate from 8 hashed wedges (closed fraction times
  * degree (degree - 1) / 2; wedge choices are splitmix64 of (seed, vertex,
  * sample)), and the h-index of the neighbour degrees (a core-number
- * estimate).  Rows must be sorted ascending.  Vertices of degree >= 128 are
- * listed in a buffer the library allocates per device on first use (4 (n + 64)
- * bytes, grown for larger n) and processed one workgroup each; concurrent
- * calls on one device from different streams share that buffer and race.
- * Errors: GCOLOR_EINVAL (n < 0, NULL pointers with n > 0), GCOLOR_EHIP.
+ * estimate).  Rows must be sorted ascending.  workspace: device memory of
+ * gcolor_features_workspace_bytes(n) bytes owned by the caller (vertices of
+ * degree >= 128 are listed there and processed one workgroup each); calls
+ * on different streams need workspaces of their own.  Asynchronous on
+ * `stream`.  Errors: GCOLOR_EINVAL (n < 0, NULL pointers with n > 0),
+ * GCOLOR_EWORKSPACE, GCOLOR_EHIP.
  */
+size_t gcolor_features_workspace_bytes(int32_t n);
 int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
-                    gcolor_stream_t stream);
+                    void* workspace, size_t ws_bytes, gcolor_stream_t stream);
 
 /* Adds sum and sum of squares of log1p(feature) per feature (double[16],
  * device, caller zeroes it) over n vertices. */
 int gcolor_feature_stats(int64_t n, const float* feat, double* acc, gcolor_stream_t stream);
+
+/* norm (float[16], device) from the sums of gcolor_feature_stats over count
+ * vertices: per feature the mean and the population standard deviation of
+ * log1p(feature), the variance floored at 1e-12.  Errors: GCOLOR_EINVAL for
+ * count <= 0 or NULL pointers. */
+int gcolor_feature_norm(int64_t count, const double* acc, float* norm, gcolor_stream_t stream);
+
+/* Training targets (device): target[v] = log(1 + rank[v]) / log(max(n, 2))
+ * for smallest-last positions rank[v] in [0, n). */
+int gcolor_rank_targets(int32_t n, const int32_t* rank, float* target, gcolor_stream_t stream);
 
 /* score[v] for n vertices (all pointers device). */
 int gcolor_mlp_forward(int64_t n, const float* feat, const float* master, const uint16_t* wbf, const float* norm,
@@ -329,6 +392,24 @@ int gcolor_mlp_refresh_bf16(const float* master, uint16_t* wbf, gcolor_stream_t 
 /* Order-preserving float -> uint32 keys; *bad (device int) is set to 1 when
  * a score is NaN (caller zeroes it). */
 int gcolor_scores_to_keys(int64_t n, const float* score, uint32_t* keys, int32_t* bad, gcolor_stream_t stream);
+
+/*
+ * Learned priority keys in one call: features (seed as gcolor_features) ->
+ * MLP scores -> order-preserving keys, all on `stream`, for color_graph's
+ * priority argument (ties between equal keys go to the smaller id).
+ *   master, wbf, norm: the model as above (device);
+ *   keys_out  uint32[n] (device);
+ *   nan_flag  device int32 the caller zeroes; set to 1 when a score is NaN
+ *             (the keys are then unusable);
+ *   workspace device memory of gcolor_order_learned_workspace_bytes(n) bytes
+ *             (features, scores, the features' vertex list).
+ * Asynchronous: no host synchronisation, no allocation.  Errors:
+ * GCOLOR_EINVAL, GCOLOR_EWORKSPACE, GCOLOR_EHIP.
+ */
+size_t gcolor_order_learned_workspace_bytes(int32_t n);
+int gcolor_order_learned(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed,
+                         const float* master, const uint16_t* wbf, const float* norm, uint32_t* keys_out,
+                         int32_t* nan_flag, void* workspace, size_t ws_bytes, gcolor_stream_t stream);
 
 /* Exact smallest-last order on the host (host pointers): rank[v] = position
  * in the colouring order (the reverse of the removal order; each removal

@@ -68,6 +68,8 @@ def _load():
     lib.or_block_gs.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, i32p, i64p,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.or_block_gs.restype = ctypes.c_int32
+    lib.or_spec_tail.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int64, i32p, i64p, ctypes.c_int32]
+    lib.or_spec_tail.restype = ctypes.c_int32
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -128,6 +130,34 @@ def spec_sim(row_ptr, col_idx, key: Optional[np.ndarray] = None, threads: int = 
     if k < 0:
         raise RuntimeError("spec_sim: round cap %d exceeded" % max_rounds)
     return SpecResult(color[:n], int(k), fixed[:n], log[:k].copy())
+
+
+class TailResult(NamedTuple):
+    colors: np.ndarray  # int32[n]
+    rounds: int         # rounds of Algorithm 2 before the sequential finish
+    tail: int           # vertices the sequential finish coloured
+
+
+def spec_tail(row_ptr, col_idx, key: Optional[np.ndarray] = None, tail: int = 0,
+              max_rounds: Optional[int] = None) -> TailResult:
+    """Algorithm 2's rounds (as spec_sim) while more than `tail` vertices are
+    uncoloured, then the rest coloured one at a time in ascending (key, id)
+    order with first-fit (the sequential switch of section "Iterative and
+    degree of concurrency").  tail = 0 is spec_sim; tail >= n is greedy."""
+    row_ptr, col_idx = _csr_args(row_ptr, col_idx)
+    n = row_ptr.shape[0] - 1
+    if key is not None:
+        key = np.ascontiguousarray(key, dtype=np.uint32)
+    if max_rounds is None:
+        max_rounds = max(n, 1)
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    cnt = np.zeros(1, dtype=np.int64)
+    k = _load().or_spec_tail(n, _p(row_ptr, ctypes.c_int32), _p(col_idx, ctypes.c_int32),
+                             _p(key, ctypes.c_uint32), int(tail), _p(color, ctypes.c_int32),
+                             _p(cnt, ctypes.c_int64), max_rounds)
+    if k < 0:
+        raise RuntimeError("spec_tail: round cap %d exceeded" % max_rounds)
+    return TailResult(color[:n], int(k), int(cnt[0]))
 
 
 class DataflowResult(NamedTuple):
@@ -247,6 +277,31 @@ def spec_sim_py(adj: List[List[int]], key=None, trace=None) -> Tuple[List[int], 
             trace(k, list(U), dict(tent), list(R), list(color))
         U = R
     return color, k, log
+
+
+def spec_tail_py(adj: List[List[int]], key=None, tail: int = 0) -> Tuple[List[int], int]:
+    """Set-notation definition of the iterative colouring with a sequential
+    finish: rounds of Algorithm 2 (snapshot reads, losers revoked) while
+    |U| > tail, then the vertices of U one at a time in ascending (key, id)
+    order, each taking the smallest colour none of its neighbours holds."""
+    n = len(adj)
+    color = [0] * n
+    U = list(range(n))
+    k = 0
+    while len(U) > tail:
+        k += 1
+        snap = list(color)
+        tent = {v: first_fit({snap[w] for w in adj[v] if w != v}) for v in U}
+        for v in U:
+            color[v] = tent[v]
+        R = [v for v in U if any(w != v and color[w] == color[v] and _order_key(key, w) < _order_key(key, v)
+                                 for w in adj[v])]
+        for v in R:
+            color[v] = 0
+        U = R
+    for v in sorted(U, key=lambda x: _order_key(key, x)):
+        color[v] = first_fit({color[w] for w in adj[v] if w != v})
+    return color, k
 
 
 def block_gs_py(adj: List[List[int]], key=None, block: int = 1) -> Tuple[List[int], int]:

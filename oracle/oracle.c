@@ -190,6 +190,93 @@ int32_t or_spec_sim(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
 }
 
 /*
+ * Iterative colouring with a sequential finish (the closing remark of section
+ * "Iterative and degree of concurrency": once conflicts are few, switch to a
+ * sequential computation).  Rounds of Algorithm 2 exactly as in or_spec_sim
+ * run while more than `tail` vertices are uncoloured; the vertices left are
+ * then coloured one at a time in ascending (key, id) order, each with the
+ * smallest positive colour held by none of its neighbours (those committed
+ * by the rounds and those coloured earlier in the finish).  tail = 0 is
+ * or_spec_sim; tail >= n is the serial greedy or_greedy.
+ * *tail_count receives the number of vertices the finish coloured.
+ * Returns the number of rounds run (the finish is not a round), or -5 when
+ * max_rounds is exceeded.
+ */
+int32_t or_spec_tail(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* key,
+                     int64_t tail, int32_t* color, int64_t* tail_count, int32_t max_rounds) {
+    const int32_t dmax = or_max_degree(n, row_ptr);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t* S = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int32_t* tent = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int32_t* U = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int32_t* R = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int64_t* forbidden = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax + 2));
+    int64_t nU = n;
+    int64_t label = 0;
+    for (int32_t c = 0; c < dmax + 2; ++c) forbidden[c] = -1;
+    for (int32_t v = 0; v < n; ++v) {
+        color[v] = 0;
+        U[v] = v;
+    }
+    int32_t k = 0;
+    while (nU > tail) {
+        if (k >= max_rounds) { k = -5; break; }
+        ++k;
+        memcpy(S, color, sizeof(int32_t) * (size_t)n);
+        /* phase 1 against the snapshot (one stamp label per visit) */
+        for (int64_t i = 0; i < nU; ++i) {
+            const int32_t v = U[i];
+            ++label;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t w = col_idx[e];
+                if (w != v) forbidden[S[w]] = label;
+            }
+            int32_t c = 1;
+            while (forbidden[c] == label) ++c;
+            tent[v] = c;
+        }
+        for (int64_t i = 0; i < nU; ++i) color[U[i]] = tent[U[i]];
+        /* phase 2: the later vertex of a conflicting pair is re-queued */
+        int64_t nR = 0;
+        for (int64_t i = 0; i < nU; ++i) {
+            const int32_t v = U[i];
+            int lose = 0;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t w = col_idx[e];
+                if (w != v && color[w] == color[v] && or_before(key, w, v)) lose = 1;
+            }
+            if (lose) R[nR++] = v;
+        }
+        for (int64_t i = 0; i < nR; ++i) color[R[i]] = 0;
+        int32_t* t = U; U = R; R = t;
+        nU = nR;
+    }
+    if (k >= 0) {
+        /* sequential finish in ascending (key, id) order */
+        or_sort_key = key;
+        qsort(U, (size_t)nU, sizeof(int32_t), or_cmp_vertex);
+        for (int64_t i = 0; i < nU; ++i) {
+            const int32_t v = U[i];
+            ++label;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t w = col_idx[e];
+                if (w != v) forbidden[color[w]] = label;
+            }
+            int32_t c = 1;
+            while (forbidden[c] == label) ++c;
+            color[v] = c;
+        }
+        if (tail_count) *tail_count = nU;
+    }
+    free(S);
+    free(tent);
+    free(U);
+    free(R);
+    free(forbidden);
+    return k;
+}
+
+/*
  * Smallest-last ordering (Matula and Beck): repeatedly remove a vertex of
  * minimum degree in the remaining graph, ties to the smallest id; the
  * colouring order is the reverse of the removal order.  Implemented with a

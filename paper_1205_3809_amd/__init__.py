@@ -12,6 +12,8 @@ from ._binding import (  # noqa: F401
     color_graph,
     color_graph_blocks,
     color_graph_ex,
+    color_graph_async,
+    stats_from_device,
     library_path,
     strerror,
     version,
@@ -20,10 +22,11 @@ from ._binding import (  # noqa: F401
     FLAG_STATS,
     FLAG_PLAIN,
     FLAG_DATAFLOW,
+    FLAG_SERIAL_TAIL,
     PROF_PHASE1,
     PROF_PHASE2,
     PROF_INC_A,
-    PROF_INC_B,
+    PROF_LISTS,
     PROF_INC_C,
     PROF_FLOW,
     get_tuning,
@@ -32,6 +35,8 @@ from ._binding import (  # noqa: F401
     get_kernel_blocks,
     set_kernel_blocks,
     get_round_cap,
+    get_serial_tail,
+    set_serial_tail,
     set_round_cap,
     profile,
     profile_read,

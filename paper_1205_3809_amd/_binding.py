@@ -20,6 +20,7 @@ FLAG_VALIDATE = 1
 FLAG_STATS = 2
 FLAG_PLAIN = 4
 FLAG_DATAFLOW = 8  # dataflow colouring (Algorithm 3): the serial greedy's result
+FLAG_SERIAL_TAIL = 16  # rounds, then the last vertices one at a time (a different colouring)
 
 
 class GColorError(RuntimeError):
@@ -30,7 +31,7 @@ class GColorError(RuntimeError):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("num_colors", ctypes.c_int32),
-                ("edge_work", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("edge_work", ctypes.c_int64), ("status", ctypes.c_int32), ("serial_tail", ctypes.c_int32)]
 
 
 class _Round(ctypes.Structure):
@@ -46,6 +47,7 @@ class Stats(NamedTuple):
     round_log: List[Tuple[int, int, int]]  # (k, |U_k|, E_k)
     # per round: (committed, dirty, dirty degree sum, row entries the dirty pass read)
     detail: List[Tuple[int, int, int, int]]
+    serial_tail: int = 0  # vertices the sequential finish coloured (FLAG_SERIAL_TAIL)
 
 
 def library_path() -> str:
@@ -66,6 +68,9 @@ def _load():
     lib.color_graph_ex.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_uint32,
                                    ctypes.POINTER(_Stats), ctypes.POINTER(_Round), ctypes.c_int32, vp]
     lib.color_graph_ex.restype = ctypes.c_int
+    lib.color_graph_async.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                      ctypes.c_int32, ctypes.c_uint32, vp, vp]
+    lib.color_graph_async.restype = ctypes.c_int
     lib.gcolor_strerror.argtypes = [ctypes.c_int]
     lib.gcolor_strerror.restype = ctypes.c_char_p
     lib.gcolor_version.argtypes = []
@@ -74,14 +79,18 @@ def _load():
     lib.gcolor_set_tuning.restype = ctypes.c_int
     lib.gcolor_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.gcolor_set_batch_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
-    lib.gcolor_set_kernel_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gcolor_set_kernel_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.gcolor_set_kernel_blocks.restype = ctypes.c_int
-    lib.gcolor_get_kernel_blocks.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 3
+    lib.gcolor_get_kernel_blocks.argtypes = [ctypes.POINTER(ctypes.c_int32)] * 2
     lib.gcolor_blocks_workspace_bytes.argtypes = [ctypes.c_int32]
     lib.gcolor_blocks_workspace_bytes.restype = ctypes.c_size_t
     lib.color_graph_blocks.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                        ctypes.POINTER(_Stats), vp]
     lib.color_graph_blocks.restype = ctypes.c_int
+    lib.gcolor_set_serial_tail.argtypes = [ctypes.c_int32]
+    lib.gcolor_set_serial_tail.restype = ctypes.c_int
+    lib.gcolor_get_serial_tail.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.gcolor_get_serial_tail.restype = ctypes.c_int
     lib.gcolor_set_round_cap.argtypes = [ctypes.c_int32]
     lib.gcolor_set_round_cap.restype = ctypes.c_int
     lib.gcolor_get_round_cap.argtypes = [ctypes.POINTER(ctypes.c_int32)]
@@ -101,8 +110,16 @@ def _load():
     lib.color_graph_batch.restype = ctypes.c_int
     lib.gcolor_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.gcolor_wall_clock_khz.restype = ctypes.c_int
-    lib.gcolor_features.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_uint64, vp, vp]
+    lib.gcolor_features_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.gcolor_features_workspace_bytes.restype = ctypes.c_size_t
+    lib.gcolor_features.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_uint64, vp, vp, ctypes.c_size_t, vp]
     lib.gcolor_feature_stats.argtypes = [ctypes.c_int64, vp, vp, vp]
+    lib.gcolor_feature_norm.argtypes = [ctypes.c_int64, vp, vp, vp]
+    lib.gcolor_rank_targets.argtypes = [ctypes.c_int32, vp, vp, vp]
+    lib.gcolor_order_learned_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.gcolor_order_learned_workspace_bytes.restype = ctypes.c_size_t
+    lib.gcolor_order_learned.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_uint64, vp, vp, vp, vp, vp, vp,
+                                         ctypes.c_size_t, vp]
     lib.gcolor_mlp_forward.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     lib.gcolor_mlp_partial_floats.argtypes = [ctypes.c_int32]
     lib.gcolor_mlp_partial_floats.restype = ctypes.c_size_t
@@ -112,7 +129,8 @@ def _load():
     lib.gcolor_mlp_refresh_bf16.argtypes = [vp, vp, vp]
     lib.gcolor_scores_to_keys.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
     lib.gcolor_smallest_last_host.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
-    for f in ("gcolor_features", "gcolor_feature_stats", "gcolor_mlp_forward", "gcolor_mlp_grad", "gcolor_mlp_adam",
+    for f in ("gcolor_features", "gcolor_feature_stats", "gcolor_feature_norm", "gcolor_rank_targets",
+              "gcolor_order_learned", "gcolor_mlp_forward", "gcolor_mlp_grad", "gcolor_mlp_adam",
               "gcolor_mlp_refresh_bf16", "gcolor_scores_to_keys", "gcolor_smallest_last_host"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
@@ -201,7 +219,49 @@ def color_graph_ex(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optio
             log.append((int(logbuf[i].round), int(logbuf[i].worklist), int(logbuf[i].edge_work)))
             detail.append((int(logbuf[i].committed), int(logbuf[i].dirty), int(logbuf[i].dirty_edges),
                            int(logbuf[i].scanned)))
-    return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), log, detail)
+    return colors_out, Stats(int(st.rounds), int(st.num_colors), int(st.edge_work), log, detail,
+                             int(st.serial_tail))
+
+
+STATS_DTYPE_WORDS = 6  # gcolor_stats_t as int32 words: rounds, colours, edge work (2), status, serial tail
+
+
+def color_graph_async(row_ptr: torch.Tensor, col_idx: torch.Tensor, nnz: int, workspace: torch.Tensor,
+                      max_rounds: int, priority: Optional[torch.Tensor] = None,
+                      colors_out: Optional[torch.Tensor] = None, stats_out: Optional[torch.Tensor] = None,
+                      validate: bool = False, stream=None):
+    """Stream-ordered colouring with a round budget: nothing is read back and
+    nothing allocated by the library, so the call can be captured in a HIP
+    graph.  stats_out: int32[6] device tensor receiving gcolor_stats_t (see
+    stats_from_device).  Returns (colors_out, stats_out)."""
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must have n+1 entries")
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    pr = _dev_ptr(priority, "priority", _KEY, n)
+    if colors_out is None:
+        colors_out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    co = _dev_ptr(colors_out, "colors_out", _I32, n)
+    if stats_out is None:
+        stats_out = torch.zeros(STATS_DTYPE_WORDS, dtype=torch.int32, device=row_ptr.device)
+    so = _dev_ptr(stats_out, "stats_out", _I32, STATS_DTYPE_WORDS)
+    ws = _dev_ptr(workspace, "workspace", (torch.uint8, torch.int8, torch.int32, torch.int64))
+    ws_bytes = workspace.numel() * workspace.element_size()
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.color_graph_async(n, int(nnz), rp, ci, pr, co, ws, ws_bytes, int(max_rounds),
+                                    FLAG_VALIDATE if validate else 0, so, _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "color_graph_async")
+    return colors_out, stats_out
+
+
+def stats_from_device(stats_out: torch.Tensor):
+    """(rounds, num_colors, edge_work, status) from a stats tensor that
+    color_graph_async filled (synchronises with its stream)."""
+    w = stats_out.cpu().numpy()
+    edge = int(w[2].astype("uint32")) | (int(w[3]) << 32)
+    return int(w[0]), int(w[1]), edge, int(w[4])
 
 
 def blocks_workspace_bytes(n: int) -> int:
@@ -273,16 +333,16 @@ def get_tuning():
     return list(arr), int(bpc.value)
 
 
-def set_kernel_blocks(blocks_a: int = 0, blocks_b: int = 0, blocks_c: int = 0) -> None:
-    """Blocks per CU of the three round kernels of the incremental engine
+def set_kernel_blocks(blocks_a: int = 0, blocks_c: int = 0) -> None:
+    """Blocks per CU of the two round kernels of the incremental engine
     (0: the common blocks_per_cu of set_tuning); speed only."""
-    rc = _lib.gcolor_set_kernel_blocks(int(blocks_a), int(blocks_b), int(blocks_c))
+    rc = _lib.gcolor_set_kernel_blocks(int(blocks_a), int(blocks_c))
     if rc != 0:
         raise GColorError(rc, "gcolor_set_kernel_blocks")
 
 
 def get_kernel_blocks():
-    v = [ctypes.c_int32() for _ in range(3)]
+    v = [ctypes.c_int32() for _ in range(2)]
     _lib.gcolor_get_kernel_blocks(*[ctypes.byref(x) for x in v])
     return tuple(int(x.value) for x in v)
 
@@ -293,6 +353,19 @@ def set_round_cap(max_rounds: int = 0) -> None:
     rc = _lib.gcolor_set_round_cap(int(max_rounds))
     if rc != 0:
         raise GColorError(rc, "gcolor_set_round_cap")
+
+
+def set_serial_tail(max_vertices: int) -> None:
+    """Vertices left to the sequential finish of FLAG_SERIAL_TAIL (1..8192)."""
+    rc = _lib.gcolor_set_serial_tail(int(max_vertices))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_set_serial_tail")
+
+
+def get_serial_tail() -> int:
+    v = ctypes.c_int32()
+    _lib.gcolor_get_serial_tail(ctypes.byref(v))
+    return int(v.value)
 
 
 def get_round_cap() -> int:
@@ -319,7 +392,7 @@ def get_batch_tuning():
 PROF_PHASE1 = 0   # plain engine: tentative colouring
 PROF_PHASE2 = 1   # plain engine: conflict detection + compaction
 PROF_INC_A = 2    # incremental: tentative colours of dirty vertices
-PROF_INC_B = 3    # no kernel (the incremental counters are completed in PROF_INC_C)
+PROF_LISTS = 3    # incremental: dirty lists of the next round, in vertex order
 PROF_INC_C = 4    # incremental: commit + push
 PROF_FLOW = 5     # dataflow: one round
 

@@ -71,7 +71,7 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
 
     def setup(setting):
         B.set_tuning(setting[:4], setting[4])
-        B.set_kernel_blocks(*setting[5:8])
+        B.set_kernel_blocks(*setting[5:7])
 
     def run(setting):
         setup(setting)
@@ -84,9 +84,7 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     best_t, trials = t0, [{"setting": list(cur), "ms": round(t0, 4)}]
     for _ in range(passes):
         changed = False
-        for i in range(8):
-            if i == 6:
-                continue  # the second round kernel's blocks: no kernel uses them
+        for i in range(7):
             for v in (BIN_CANDIDATES[i] if i < 4 else BPC_CANDIDATES if i == 4 else KERNEL_BLOCK_CANDIDATES):
                 trial = list(cur)
                 trial[i] = v
@@ -104,7 +102,7 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
         if not changed:
             break
     setup(cur)
-    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "kernel_blocks": cur[5:8],
+    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "kernel_blocks": cur[5:7],
             "ms": round(best_t, 4), "start_ms": round(t0, 4), "trials": trials}
 
 
@@ -174,7 +172,10 @@ def apply(table, name: str, arch_name: Optional[str] = None) -> Optional[Dict]:
         return None
     if entry["kind"] == "single":
         B.set_tuning(entry["bin_limits"], entry["blocks_per_cu"])
-        B.set_kernel_blocks(*entry.get("kernel_blocks", (0, 0, 0)))
+        kb = list(entry.get("kernel_blocks", (0, 0)))
+        if len(kb) == 3:  # older entries: (dirty kernel, unused, commit kernel)
+            kb = [kb[0], kb[2]]
+        B.set_kernel_blocks(*kb)
     elif entry["kind"] == "batch":
         B.set_batch_tuning(entry["block_threads"], entry["lds_factor"], entry["lds_max_vertices"])
     else:

@@ -64,6 +64,11 @@
 
 namespace {
 
+// Load the next chunks' vertex data ahead in the dirty-vertex kernel.
+#ifndef GC_PREFETCH_A
+#define GC_PREFETCH_A 1
+#endif
+
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 // Rows longer than this (the register cache of a wave) keep an active copy in
@@ -119,6 +124,7 @@ struct Args {
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
     int* __restrict__ lists;       // [kSets][kBins][n]
     unsigned* __restrict__ dbits;  // (incremental) 3 dirty bitmaps of nwords words
+    unsigned* __restrict__ bplane; // (incremental) each vertex's degree bin as 3 bit planes of nwords words
     int nwords;
     Ctl* ctl;
     long long* __restrict__ log;   // [kMaxLog][kLogW]
@@ -131,6 +137,11 @@ struct Args {
     unsigned* __restrict__ hF;
     int* __restrict__ act;
     long long nnz;
+    // sequential finish: rounds stop once at most `tail` vertices are
+    // uncoloured (0: rounds to the end)
+    int tail;
+    const uint32_t* __restrict__ key;  // the priority array (NULL: natural)
+    int* __restrict__ bcnt;            // (incremental) per-block bin counts of the dirty-list build
 };
 
 struct Stage {
@@ -172,6 +183,35 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int lane) {
     }
 }
 
+// Per-wavefront list stage of the incremental round kernels: each wavefront
+// walks its own chunks and flushes its own stage, with no workgroup barrier.
+constexpr int kWaves = kBlock / kWave;
+__host__ __device__ constexpr int wstage_cap(int b) {
+    return b == 0 ? 512 : b == 1 ? 256 : b == 2 ? 128 : b == 3 ? 64 : 32;
+}
+__host__ __device__ constexpr int wstage_off(int b) {
+    return b == 0 ? 0 : b == 1 ? 512 : b == 2 ? 768 : b == 3 ? 896 : 960;
+}
+constexpr int kWStageTotal = 992;
+
+struct WaveStage {
+    int cnt[kBins];
+    int base[kBins];
+    int q[kWStageTotal];
+};
+
+__device__ __forceinline__ int scap(const Stage*, int b) { return stage_cap(b); }
+__device__ __forceinline__ int soff(const Stage*, int b) { return stage_off(b); }
+__device__ __forceinline__ int scap(const WaveStage*, int b) { return wstage_cap(b); }
+__device__ __forceinline__ int soff(const WaveStage*, int b) { return wstage_off(b); }
+
+// Lanes of one wavefront see each other's LDS writes after this.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void stage_init(Stage* st) {
     if (threadIdx.x < kBins) st->cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -181,7 +221,8 @@ __device__ __forceinline__ void stage_init(Stage* st) {
 // `set`: one LDS atomic per wavefront and bin; entries beyond the stage
 // capacity go straight to the global list.  Safe in divergent code: every
 // active lane must call it, the leader of each ballot is an active lane.
-__device__ __forceinline__ void stage_append(const Args& a, Stage* st, bool pred, int v, int deg, int set) {
+template <class ST>
+__device__ __forceinline__ void stage_append(const Args& a, ST* st, bool pred, int v, int deg, int set) {
     const uint64_t any = __ballot(pred);
     if (any == 0) return;
     const int b = pred ? bin_of(deg, a.cfg) : -1;
@@ -196,8 +237,8 @@ __device__ __forceinline__ void stage_append(const Args& a, Stage* st, bool pred
         base = __shfl(base, leader);
         if (b == k) {
             const int slot = base + __popcll(m & __lanemask_lt());
-            if (slot < stage_cap(k)) {
-                st->q[stage_off(k) + slot] = v;
+            if (slot < scap(st, k)) {
+                st->q[soff(st, k) + slot] = v;
             } else {
                 const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
                 list_ptr(a, set, k)[g] = v;
@@ -208,11 +249,12 @@ __device__ __forceinline__ void stage_append(const Args& a, Stage* st, bool pred
 
 // Staged append of one vertex by one lane (sparse appends from inside row
 // loops): a per-lane LDS atomic, no wavefront-wide ballots.
-__device__ __forceinline__ void stage_push(const Args& a, Stage* st, int v, int deg, int set) {
+template <class ST>
+__device__ __forceinline__ void stage_push(const Args& a, ST* st, int v, int deg, int set) {
     const int k = bin_of(deg, a.cfg);
     const int slot = atomicAdd(&st->cnt[k], 1);
-    if (slot < stage_cap(k)) {
-        st->q[stage_off(k) + slot] = v;
+    if (slot < scap(st, k)) {
+        st->q[soff(st, k) + slot] = v;
     } else {
         const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
         list_ptr(a, set, k)[g] = v;
@@ -220,8 +262,44 @@ __device__ __forceinline__ void stage_push(const Args& a, Stage* st, int v, int 
 }
 
 // Staged append where the degree must still be looked up.
-__device__ __forceinline__ void stage_append_lookup(const Args& a, Stage* st, bool pred, int v, int set) {
+template <class ST>
+__device__ __forceinline__ void stage_append_lookup(const Args& a, ST* st, bool pred, int v, int set) {
     if (pred) stage_push(a, st, v, a.row_ptr[v + 1] - a.row_ptr[v], set);
+}
+
+// Per-wavefront stage: clear (wave-uniform call).
+__device__ __forceinline__ void wstage_init(WaveStage* st) {
+    if (__lane_id() < kBins) st->cnt[__lane_id()] = 0;
+    wave_sync();
+}
+
+// Move a wavefront's staged entries to the global lists (wave-uniform call).
+__device__ __forceinline__ void wstage_flush(const Args& a, WaveStage* st, int set) {
+    wave_sync();
+    const int lane = __lane_id();
+    if (lane < kBins) {
+        const int c = min(st->cnt[lane], wstage_cap(lane));
+        st->base[lane] = c ? atomicAdd(&a.ctl->cnt[set][lane], c) : 0;
+        st->cnt[lane] = c;
+    }
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        int* dst = list_ptr(a, set, b) + st->base[b];
+        for (int i = lane; i < st->cnt[b]; i += kWave) dst[i] = st->q[wstage_off(b) + i];
+    }
+    wave_sync();
+    if (lane < kBins) st->cnt[lane] = 0;
+    wave_sync();
+}
+
+// Flush when any bin of the wavefront's stage is at least half full.
+__device__ __forceinline__ void wstage_maybe_flush(const Args& a, WaveStage* st, int set) {
+    wave_sync();
+    bool full = false;
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) full |= st->cnt[b] * 2 >= wstage_cap(b);
+    if (full) wstage_flush(a, st, set);
 }
 
 // Move the staged entries to the global lists (block-uniform call).
@@ -561,6 +639,7 @@ __device__ __forceinline__ bool is_dirty(const unsigned* __restrict__ bits, int 
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
     __shared__ Stage stg;
+    if (a.ctl->err) return;  // the CSR failed validation: nothing is read
     stage_init(&stg);
     S* st = static_cast<S*>(a.st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -608,6 +687,19 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
                 const int h = hb + __popcll(hm & __lanemask_lt());
                 a.hid[v] = h;
                 a.hrow[h] = make_int4(sp, deg - sp, 0, 0);
+            }
+        }
+        // the degree bin as three bit planes, 32 vertices a word (a
+        // wavefront holds 64 consecutive vertices: two words)
+        {
+            const int bn = ok ? bin_of(deg, a.cfg) : 0;
+            const int lane = __lane_id();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const unsigned long long m = __ballot((bn >> q) & 1);
+                const int word = v >> 5;
+                if ((lane & 31) == 0 && word < a.nwords)
+                    a.bplane[(size_t)q * a.nwords + word] = (unsigned)(lane ? (m >> 32) : m);
             }
         }
         stage_append(a, &stg, ok && sp == 0, v, deg, cset(1));
@@ -753,7 +845,7 @@ __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __rest
 // in flight together instead of waiting on each entry in turn.  Positions
 // from e on hold w itself and are skipped.
 template <int GS, int N>
-__device__ __forceinline__ void inc_a_eval_staged(const Args& a, Stage* stg, const unsigned* __restrict__ bits, int k,
+__device__ __forceinline__ void inc_a_eval_staged(const Args& a, WaveStage* stg, const unsigned* __restrict__ bits, int k,
                                                   int w, int start, int e, int lim, int now, int old, const int* xs,
                                                   const int* sv, int* cnt, bool* dlow) {
     // which entries need their dirty bit: uncommitted preceding neighbours,
@@ -845,7 +937,7 @@ __device__ __forceinline__ bool hv_keep(int c) { return c < 0 || c > 64 + kFFBit
 // counter and of the preceding-dirty flag, the later neighbours' counter
 // updates (as inc_a_eval), and the compaction of its active row.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, int w, int s, int old, int lig,
+__device__ __forceinline__ void inc_a_heavy(const Args& a, WaveStage* stg, int k, int w, int s, int old, int lig,
                                             uint64_t* red, int* shc, unsigned* bm, int* cc, int* now_out,
                                             int* cnt_out, bool* dlow_out, int* len_out) {
     S* st = static_cast<S*>(a.st);
@@ -1013,7 +1105,7 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, Stage* stg, int k, in
 
 // Second pass over a row too long for the register cache: re-gather.
 template <int STRIDE, typename S>
-__device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, const S* __restrict__ st,
+__device__ __forceinline__ void inc_a_pass2_gather(const Args& a, WaveStage* stg, const S* __restrict__ st,
                                                    const unsigned* __restrict__ bits, int k, int w, int start, int e,
                                                    int lim, int now, int old, int* cnt, bool* dlow) {
     const int cs = cset(k);
@@ -1040,17 +1132,51 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, Stage* stg, co
 // to the candidate list, as ~w while preceding dirty neighbours leave its
 // count open, as w when the count is final and 0.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, int k, int w, int deg,
+__device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
                                              long long* dedges);
 
+// What a dirty vertex's processing reads first: its id, row bounds, split
+// point and state word.  The wavefront walk loads it one chunk ahead (no
+// other group writes these words of w during the kernel).
+struct VInfo {
+    int w, s, e, sp, old;
+};
+
+template <typename S>
+__device__ __forceinline__ VInfo load_vinfo(const Args& a, int w) {
+    VInfo r;
+    r.w = w;
+    if (w >= 0) {
+        r.s = a.row_ptr[w];
+        r.e = a.row_ptr[w + 1];
+        r.sp = a.split[w];
+        r.old = static_cast<const S*>(a.st)[w];
+    } else {
+        r.s = r.e = r.sp = r.old = 0;
+    }
+    return r;
+}
+
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, int w, int lig,
+__device__ __forceinline__ void inc_a_vertex_pre(const Args& a, WaveStage* stg, int k, const VInfo& vi, int lig,
+                                                 uint64_t* red, int* shc, unsigned* ffbm, int* cc,
+                                                 long long* dedges);
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_vertex(const Args& a, WaveStage* stg, int k, int w, int lig,
                                              uint64_t* red, int* shc, unsigned* ffbm, int* cc, long long* dedges) {
+    inc_a_vertex_pre<GS, S>(a, stg, k, load_vinfo<S>(a, w), lig, red, shc, ffbm, cc, dedges);
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_a_vertex_pre(const Args& a, WaveStage* stg, int k, const VInfo& vi, int lig,
+                                                 uint64_t* red, int* shc, unsigned* ffbm, int* cc,
+                                                 long long* dedges) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
-    const int s = a.row_ptr[w], e = a.row_ptr[w + 1];
-    const int old = st[w];
+    const int w = vi.w, s = vi.s, e = vi.e;
+    const int old = vi.old;
     if constexpr (GS == kBlock || GS == kWave) {
         if (e - s > kHeavyDeg) {
             unsigned* bm = GS == kBlock ? ffbm : ffbm + (threadIdx.x / kWave) * kFFWords;
@@ -1062,7 +1188,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, i
             return;
         }
     }
-    const int lim = s + a.split[w];
+    const int lim = s + vi.sp;
     const bool cached = (e - s) <= kCache * GS;
     int xs[kCache], sv[kCache];
     if (cached) {
@@ -1119,7 +1245,7 @@ __device__ __forceinline__ void inc_a_vertex(const Args& a, Stage* stg, int k, i
 // Group totals of the counter and the preceding-dirty flag; state, counter
 // and list appends of dirty vertex w.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, int k, int w, int deg,
+__device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
                                              long long* dedges) {
     S* st = static_cast<S*>(a.st);
@@ -1153,24 +1279,65 @@ __device__ __forceinline__ void inc_a_finish(const Args& a, Stage* stg, int k, i
     stage_append(a, stg, to_b || cand, to_b ? ~w : w, deg, cs);
 }
 
-template <int GS, typename S>
-__device__ __forceinline__ void inc_a_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt,
-                                            int local, unsigned* ffbm, long long* dedges) {
-    constexpr int CV = kBlock / GS;
-    const int lig = threadIdx.x & (GS - 1);
-    const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) inc_a_vertex<GS, S>(a, stg, k, list[idx], lig, nullptr, nullptr, ffbm, nullptr, dedges);
+// Chunk space of the group tiers (bins 0..3) for wavefront walks: a chunk
+// is what one wavefront takes at once, 64 / 16 / 4 / 1 vertices for bins
+// 0 / 1 / 2 / 3 (64 / 4 / 1 lanes per vertex ... one wavefront per
+// vertex); bins ordered 3, 2, 1, 0 (heaviest first).
+__host__ __device__ constexpr int wchunk(int b) { return b == 0 ? 64 : b == 1 ? 16 : b == 2 ? 4 : 1; }
+
+struct WaveMap {
+    int cnt[4];
+    int start[4];
+    int total;
+};
+
+__device__ __forceinline__ WaveMap make_wave_map(const Ctl* ctl, int set) {
+    WaveMap m;
+    int tot = 0;
+    for (int b = 3; b >= 0; --b) {
+        m.cnt[b] = ctl->cnt[set][b];
+        m.start[b] = tot;
+        tot += (m.cnt[b] + wchunk(b) - 1) / wchunk(b);
+    }
+    m.total = tot;
+    return m;
+}
+
+__device__ __forceinline__ int wave_chunk_bin(const WaveMap& m, int c) {
+    return 3 - (c >= m.start[2]) - (c >= m.start[1]) - (c >= m.start[0]);
+}
+
+__device__ __forceinline__ int pick4(const int* x, int b) {
+    return b == 0 ? x[0] : b == 1 ? x[1] : b == 2 ? x[2] : x[3];
+}
+
+// List entry that lane `lane` takes in wavefront chunk c of list set `set`
+// (its group's vertex), or INT_MIN when the chunk or the group is past the
+// end.
+__device__ __forceinline__ int wave_chunk_entry(const Args& a, const WaveMap& m, int set, int c, int lane) {
+    if (c >= m.total) return INT_MIN;
+    const int b = wave_chunk_bin(m, c);
+    const int idx = (c - pick4(m.start, b)) * wchunk(b) + lane / (kWave / wchunk(b));
+    return idx < pick4(m.cnt, b) ? list_ptr(a, set, b)[idx] : INT_MIN;
 }
 
 // Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
-// (its list is still intact), so that round k+1 can reuse it.
+// (its list is still intact), so that round k+1 can reuse it.  The
+// workgroup tier runs first, one vertex per workgroup; then every wavefront
+// walks its own chunks of the group tiers with no workgroup barrier, with
+// the list entry of the chunk after next and the row bounds, split point
+// and state word of the next chunk loaded before the current one is
+// processed.
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
-    __shared__ uint64_t red[kBlock / kWave];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_inc_a(Args a, int k) {
+    __shared__ uint64_t red[kWaves];
     __shared__ int shc[8];
-    __shared__ Stage stg;
-    __shared__ unsigned ffbm[(kBlock / kWave) * kFFWords];
+    __shared__ WaveStage wstg[kWaves];
+    __shared__ unsigned ffbm[kWaves * kFFWords];
     __shared__ int cc[2];
+    // sequential finish requested and at most `tail` vertices left: this
+    // round and every later one do nothing (the finish colours the rest)
+    if (a.tail > 0 && (long long)a.n - (long long)a.ctl->committed <= a.tail) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the list that this round's commits fill (round k-2's dirty list,
         // whose bitmap words k_inc_a of round k-1 cleared)
@@ -1186,11 +1353,13 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
         // kernel's blocks: the previous kernel cleared them, not block 0 here,
         // so that no block adds before they are cleared
     }
-    const ChunkMap m = make_map(a.ctl, dlist(k));
+    const int set = dlist(k);
+    const int n4 = a.ctl->cnt[set][4];
+    const WaveMap m = make_wave_map(a.ctl, set);
     int nprev = 0;
     for (int b = 0; b < kBins; ++b) nprev += a.ctl->cnt[dlist(k - 1)][b];
     const int clear_blocks = (nprev + kBlock - 1) / kBlock;
-    if ((int)blockIdx.x >= max(m.total, clear_blocks)) return;
+    if ((int)blockIdx.x >= max(max(n4, (m.total + kWaves - 1) / kWaves), clear_blocks)) return;
     {
         // every bit of that bitmap belongs to a previous dirty vertex, so the
         // words holding them can be zeroed whole
@@ -1201,16 +1370,45 @@ __global__ __launch_bounds__(kBlock) void k_inc_a(Args a, int k) {
             for (int i = blockIdx.x * kBlock + threadIdx.x; i < c; i += gridDim.x * kBlock) pbits[l[i] >> 5] = 0u;
         }
     }
-    stage_init(&stg);
+    const int cs = cset(k);
+    WaveStage* stg = &wstg[threadIdx.x / kWave];
+    wstage_init(stg);
     long long dedges[2] = {0, 0};  // degree sum and scanned entries of the dirty rows
-#define A_GS(GS, L, C, LOC) inc_a_chunk<GS, S>(a, &stg, k, L, C, LOC, ffbm, dedges)
-#define A_BLOCK(V) inc_a_vertex<kBlock, S>(a, &stg, k, (V), (int)threadIdx.x, red, shc, ffbm, cc, dedges)
-#define A_AFTER() stage_maybe_flush(a, &stg, cset(k))
-    GC_WALK_CHUNKS(a, m, dlist(k), A_GS, A_BLOCK, A_AFTER)
-#undef A_GS
-#undef A_BLOCK
-#undef A_AFTER
-    stage_flush(a, &stg, cset(k));
+    const int* l4 = list_ptr(a, set, 4);
+    for (int c = blockIdx.x; c < n4; c += gridDim.x) {
+        inc_a_vertex<kBlock, S>(a, stg, k, l4[c], (int)threadIdx.x, red, shc, ffbm, cc, dedges);
+        wstage_maybe_flush(a, stg, cs);
+    }
+    const int lane = __lane_id();
+    const int W = gridDim.x * kWaves;
+    int c = blockIdx.x * kWaves + (int)threadIdx.x / kWave;
+#if GC_PREFETCH_A
+    int e2 = wave_chunk_entry(a, m, set, c + W, lane);
+    VInfo nxt = load_vinfo<S>(a, max(wave_chunk_entry(a, m, set, c, lane), -1));
+#endif
+    for (; c < m.total; c += W) {
+#if GC_PREFETCH_A
+        const VInfo cur = nxt;
+        nxt = load_vinfo<S>(a, max(e2, -1));
+        e2 = wave_chunk_entry(a, m, set, c + 2 * W, lane);
+#else
+        const VInfo cur = load_vinfo<S>(a, max(wave_chunk_entry(a, m, set, c, lane), -1));
+#endif
+        if (cur.w >= 0) {
+            switch (wave_chunk_bin(m, c)) {
+                case 0: inc_a_vertex_pre<1, S>(a, stg, k, cur, 0, nullptr, nullptr, ffbm, nullptr, dedges); break;
+                case 1: inc_a_vertex_pre<4, S>(a, stg, k, cur, lane & 3, nullptr, nullptr, ffbm, nullptr, dedges); break;
+                case 2:
+                    inc_a_vertex_pre<16, S>(a, stg, k, cur, lane & 15, nullptr, nullptr, ffbm, nullptr, dedges);
+                    break;
+                default:
+                    inc_a_vertex_pre<kWave, S>(a, stg, k, cur, lane, nullptr, nullptr, ffbm, nullptr, dedges);
+                    break;
+            }
+        }
+        wstage_maybe_flush(a, stg, cs);
+    }
+    wstage_flush(a, stg, cs);
     if (k - 1 < kMaxLog) {
         block_add_log(dedges[0], &a.log[kLogW * (k - 1) + 3]);
         block_add_log(dedges[1], &a.log[kLogW * (k - 1) + 4]);
@@ -1249,18 +1447,18 @@ __device__ __forceinline__ int inc_b_count(const int* __restrict__ row, const S*
 // Dirty marks from committed vertex v (colour t) over its later entries
 // start, start + STRIDE, ... < e: an entry u whose word is t is uncoloured
 // with tentative colour t, so its tentative colour must move in round k+1;
-// the first mark of u appends it to round k+1's dirty list.  A neighbour
+// its bit is set in round k+1's bitmap (the round's dirty lists are built
+// from the bitmap after this kernel, in ascending vertex order).  A neighbour
 // committed in this same kernel holds a colour different from t (two
 // adjacent vertices with equal tentative colours cannot both have counter
 // 0), so reading its word before or after its commit gives no match.  Eight
 // entries per step, in stages (state reads, bitmap reads, then the atomics),
 // so that each stage's memory operations of a lane are in flight together.
 template <int STRIDE, typename S>
-__device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__ row, Stage* stg,
-                                          const S* __restrict__ st, int k, int v, int t, int start, int e) {
+__device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__ row, const S* __restrict__ st,
+                                          int k, int v, int t, int start, int e) {
     constexpr int U = 8;
     unsigned* nbits = dbits(a, k + 1);
-    const int ds = dlist(k + 1);
     for (int p0 = start; p0 < e; p0 += U * STRIDE) {
         int u[U], su[U];
 #pragma unroll
@@ -1270,9 +1468,7 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) su[j] = st[u[j]];
-        // round k+1's bitmap is clear when this kernel starts, so the atomic
-        // that sets a bit is its first mark; a plain read first skips most
-        // repeats
+        // a plain read of the bitmap first skips most repeated marks
         unsigned need = 0u;
 #pragma unroll
         for (int j = 0; j < U; ++j) need |= (u[j] != v && su[j] == t ? 1u : 0u) << j;
@@ -1283,72 +1479,89 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
         unsigned setm = 0u;
 #pragma unroll
         for (int j = 0; j < U; ++j) setm |= ((word[j] >> (u[j] & 31)) & 1u ? 0u : 1u) << j;
-        unsigned prev[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) prev[j] = (setm >> j & 1u) ? atomicOr(&nbits[u[j] >> 5], 1u << (u[j] & 31)) : ~0u;
-#pragma unroll
-        for (int j = 0; j < U; ++j) stage_append_lookup(a, stg, !((prev[j] >> (u[j] & 31)) & 1u), u[j], ds);
+        for (int j = 0; j < U; ++j)
+            if (setm >> j & 1u) atomicOr(&nbits[u[j] >> 5], 1u << (u[j] & 31));
     }
 }
 
 // One entry of the candidate list: a candidate v (>= 0) commits if its
 // counter is 0; ~w (a dirty vertex with preceding dirty neighbours) first
 // has its counter completed (inc_b_count) and commits if the total is 0.
-template <int GS, typename S>
-__device__ __forceinline__ void inc_c_chunk(const Args& a, Stage* stg, int k, const int* list, int cnt, int local,
-                                            long long* ncom, long long* ndeg) {
-    constexpr int CV = kBlock / GS;
-    S* st = static_cast<S*>(a.st);
-    const int lig = threadIdx.x & (GS - 1);
-    const int idx = local * CV + (int)threadIdx.x / GS;
-    if (idx < cnt) {
-        const int ent = list[idx];
+// What the entry's processing reads first (entry, state word, row bounds,
+// split point, counter) comes preloaded: only the entry's own group writes
+// those words of v in this kernel.
+struct CInfo {
+    int ent, t, s, e, sp, conf;
+};
+
+template <typename S>
+__device__ __forceinline__ CInfo load_cinfo(const Args& a, int ent) {
+    CInfo r;
+    r.ent = ent;
+    if (ent != INT_MIN) {
         const int v = ent < 0 ? ~ent : ent;
-        const int t = st[v];
-        const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
-        bool commit;
-        if (ent < 0) {
-            const int* row = a.colp;
-            int lim = s + a.split[v];
-            if constexpr (GS == kWave) {
-                if (e - s > kHeavyDeg) {  // preceding segment of the active row
-                    const HeavyView hv = heavy_view(a, v, s);
-                    row = hv.row;
-                    lim = s + hv.pa;
-                }
+        r.t = static_cast<const S*>(a.st)[v];
+        r.s = a.row_ptr[v];
+        r.e = a.row_ptr[v + 1];
+        r.sp = a.split[v];
+        r.conf = a.conf[v];
+    } else {
+        r.t = r.s = r.e = r.sp = r.conf = 0;
+    }
+    return r;
+}
+
+template <int GS, typename S>
+__device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& ci, int lig,
+                                            long long* ncom, long long* ndeg) {
+    S* st = static_cast<S*>(a.st);
+    const int ent = ci.ent;
+    const int v = ent < 0 ? ~ent : ent;
+    const int t = ci.t;
+    const int s = ci.s, e = ci.e;
+    bool commit;
+    if (ent < 0) {
+        const int* row = a.colp;
+        int lim = s + ci.sp;
+        if constexpr (GS == kWave) {
+            if (e - s > kHeavyDeg) {  // preceding segment of the active row
+                const HeavyView hv = heavy_view(a, v, s);
+                row = hv.row;
+                lim = s + hv.pa;
             }
-            const int c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
-            const int tot = a.conf[v] + c;  // every lane reads before lane 0 writes (one wavefront)
-            if (lig == 0) a.conf[v] = tot;
-            commit = tot == 0;
-        } else {
-            commit = a.conf[v] == 0 && t > 0;
         }
-        if (commit) {
-            const int* row = a.colp;
-            int start = s + a.split[v], end = e;
-            if constexpr (GS == kWave) {
-                if (e - s > kHeavyDeg) {  // later segment of the active row
-                    const HeavyView hv = heavy_view(a, v, s);
-                    row = hv.row;
-                    start = hv.s1;
-                    end = hv.s1 + hv.la;
-                }
+        const int c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
+        const int tot = ci.conf + c;
+        if (lig == 0) a.conf[v] = tot;
+        commit = tot == 0;
+    } else {
+        commit = ci.conf == 0 && t > 0;
+    }
+    if (commit) {
+        const int* row = a.colp;
+        int start = s + ci.sp, end = e;
+        if constexpr (GS == kWave) {
+            if (e - s > kHeavyDeg) {  // later segment of the active row
+                const HeavyView hv = heavy_view(a, v, s);
+                row = hv.row;
+                start = hv.s1;
+                end = hv.s1 + hv.la;
             }
-            inc_c_row<GS, S>(a, row, stg, st, k, v, t, start + lig, end);
-            if (lig == 0) {
-                a.color[v] = t;
-                st[v] = (S)(-t);
-                *ncom += 1;
-                *ndeg += e - s;
-                a.ctl->rounds = k;
-            }
+        }
+        inc_c_row<GS, S>(a, row, st, k, v, t, start + lig, end);
+        if (lig == 0) {
+            a.color[v] = t;
+            st[v] = (S)(-t);
+            *ncom += 1;
+            *ndeg += e - s;
+            a.ctl->rounds = k;
         }
     }
 }
 
 template <typename S>
-__device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, int ent, int* sh, long long* ncom,
+__device__ __forceinline__ void inc_c_block(const Args& a, int k, int ent, int* sh, long long* ncom,
                                             long long* ndeg) {
     S* st = static_cast<S*>(a.st);
     const int v = ent < 0 ? ~ent : ent;
@@ -1380,7 +1593,7 @@ __device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, in
         start = hv.s1;
         end = hv.s1 + hv.la;
     }
-    inc_c_row<kBlock, S>(a, row, stg, st, k, v, t, start + (int)threadIdx.x, end);
+    inc_c_row<kBlock, S>(a, row, st, k, v, t, start + (int)threadIdx.x, end);
     __syncthreads();  // every thread has read st[v] before it is overwritten
     if (threadIdx.x == 0) {
         a.color[v] = t;
@@ -1392,11 +1605,12 @@ __device__ __forceinline__ void inc_c_block(const Args& a, Stage* stg, int k, in
 }
 
 // Round k, kernel C: commit every candidate whose counter is 0, mark its
-// dirty neighbours for round k+1.  Clears the candidate list of round k+1.
+// dirty neighbours for round k+1 in that round's bitmap.  Clears the
+// candidate list of round k+1.  Same walk as k_inc_a: the workgroup tier
+// first, then per-wavefront chunks with the next chunk's entries preloaded.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
-    __shared__ Stage stg;
-    __shared__ int sh[kBlock / kWave];
+    __shared__ int sh[kWaves];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int b = 0; b < 8; ++b) a.ctl->cnt[cset(k + 1)][b] = 0;
         if (k < kMaxLog) {  // round k+1's dirty degree sum and scanned entries
@@ -1404,23 +1618,183 @@ __global__ __launch_bounds__(kBlock) void k_inc_c(Args a, int k) {
             a.log[kLogW * k + 4] = 0;
         }
     }
-    const ChunkMap m = make_map(a.ctl, cset(k));
-    if ((int)blockIdx.x >= m.total) return;
-    stage_init(&stg);
+    const int set = cset(k);
+    const int n4 = a.ctl->cnt[set][4];
+    const WaveMap m = make_wave_map(a.ctl, set);
+    if ((int)blockIdx.x >= max(n4, (m.total + kWaves - 1) / kWaves)) return;
     long long ncom = 0, ndeg = 0;
-    const int ds = dlist(k + 1);
-#define C_GS(GS, L, C, LOC) inc_c_chunk<GS, S>(a, &stg, k, L, C, LOC, &ncom, &ndeg)
-#define C_BLOCK(V) inc_c_block<S>(a, &stg, k, (V), sh, &ncom, &ndeg)
-#define C_AFTER() stage_maybe_flush(a, &stg, ds)
-    GC_WALK_CHUNKS(a, m, cset(k), C_GS, C_BLOCK, C_AFTER)
-#undef C_GS
-#undef C_BLOCK
-#undef C_AFTER
-    stage_flush(a, &stg, ds);
+    const int* l4 = list_ptr(a, set, 4);
+    for (int c = blockIdx.x; c < n4; c += gridDim.x) inc_c_block<S>(a, k, l4[c], sh, &ncom, &ndeg);
+    const int lane = __lane_id();
+    const int W = gridDim.x * kWaves;
+    int c = blockIdx.x * kWaves + (int)threadIdx.x / kWave;
+    int e2 = wave_chunk_entry(a, m, set, c + W, lane);
+    CInfo nxt = load_cinfo<S>(a, wave_chunk_entry(a, m, set, c, lane));
+    for (; c < m.total; c += W) {
+        const CInfo cur = nxt;
+        nxt = load_cinfo<S>(a, e2);
+        e2 = wave_chunk_entry(a, m, set, c + 2 * W, lane);
+        if (cur.ent != INT_MIN) {
+            switch (wave_chunk_bin(m, c)) {
+                case 0: inc_c_entry<1, S>(a, k, cur, 0, &ncom, &ndeg); break;
+                case 1: inc_c_entry<4, S>(a, k, cur, lane & 3, &ncom, &ndeg); break;
+                case 2: inc_c_entry<16, S>(a, k, cur, lane & 15, &ncom, &ndeg); break;
+                default: inc_c_entry<kWave, S>(a, k, cur, lane, &ncom, &ndeg); break;
+            }
+        }
+    }
     block_add_log(ncom, (long long*)&a.ctl->committed);
     if (k - 1 < kMaxLog) {
         block_add_log(ncom, &a.log[kLogW * (k - 1)]);
         block_add_log(ndeg, &a.log[kLogW * (k - 1) + 1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dirty lists of round kk in ascending vertex order, built from the round's
+// bitmap after the commit kernel of round kk-1 has set it: a count pass
+// (per workgroup and bin) and a write pass (each workgroup's offsets from
+// the counts of the workgroups before it).  Processing dirty rows in vertex
+// order keeps the neighbour gathers of nearby rows close in time, which the
+// L2 caches serve better than a random order (on R-MAT, neighbour ids share
+// high bits with the row's id).  Workgroup b owns the bitmap words
+// [b W, (b+1) W), its threads consecutive slices of them, so the lists come
+// out sorted.  (A single count pass whose last workgroup computed the
+// offsets needed device-scope fences in every workgroup, which write the
+// L2s back on this multi-XCD chip: 81 us per pass instead of a few.)
+// ---------------------------------------------------------------------------
+#ifndef GC_COMPACT_WORDS
+#define GC_COMPACT_WORDS 512
+#endif
+constexpr int kCompactWordsPerBlock = GC_COMPACT_WORDS;
+constexpr int kCompactMaxBlocks = 8192;
+
+__host__ __device__ inline int compact_blocks(int nwords) {
+    const int b = (nwords + kCompactWordsPerBlock - 1) / kCompactWordsPerBlock;
+    return b < 1 ? 1 : (b > kCompactMaxBlocks ? kCompactMaxBlocks : b);
+}
+
+// This thread's slice of bitmap words.
+__device__ __forceinline__ void compact_slice(int nwords, int* w0, int* w1) {
+    const int G = gridDim.x;
+    const int per_block = (nwords + G - 1) / G;
+    const int b0 = blockIdx.x * per_block, b1 = min(nwords, b0 + per_block);
+    const int per_thread = (per_block + kBlock - 1) / kBlock;
+    *w0 = min(b1, b0 + (int)threadIdx.x * per_thread);
+    *w1 = min(b1, *w0 + per_thread);
+}
+
+// Bin counts of the dirty vertices in this thread's slice.
+// Set bits of bitmap word w whose vertex lies in degree bin b (the bit
+// planes hold each vertex's bin).
+__device__ __forceinline__ unsigned bin_mask(const Args& a, int w, int b) {
+    const unsigned p0 = a.bplane[w], p1 = a.bplane[a.nwords + w], p2 = a.bplane[2 * (size_t)a.nwords + w];
+    return ((b & 1) ? p0 : ~p0) & ((b & 2) ? p1 : ~p1) & ((b & 4) ? p2 : ~p2);
+}
+
+// Bin counts of the dirty vertices in this thread's slice.
+__device__ __forceinline__ void compact_count(const Args& a, const unsigned* __restrict__ bits, int w0, int w1,
+                                              int* c) {
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) c[b] = 0;
+    for (int w = w0; w < w1; ++w) {
+        const unsigned x = bits[w];
+        if (x == 0u) continue;
+#pragma unroll
+        for (int b = 0; b < kBins; ++b) c[b] += __popc(x & bin_mask(a, w, b));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dcount(Args a, int kk) {
+    __shared__ int part[kWaves][kBins];
+    const long long left = (long long)a.n - (long long)a.ctl->committed;
+    if (left == 0 || (a.tail > 0 && left <= a.tail)) return;  // nothing to list
+    const unsigned* bits = dbits(a, kk);
+    int w0, w1;
+    compact_slice(a.nwords, &w0, &w1);
+    int c[kBins];
+    compact_count(a, bits, w0, w1, c);
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        const int t = group_sum<kWave>(c[b]);
+        if (__lane_id() == 0) part[threadIdx.x / kWave][b] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+        int t = 0;
+        for (int q = 0; q < kWaves; ++q) t += part[q][threadIdx.x];
+        a.bcnt[blockIdx.x * 8 + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dwrite(Args a, int kk) {
+    __shared__ int base[kBins];
+    __shared__ int wsum[kWaves][kBins];
+    const long long left = (long long)a.n - (long long)a.ctl->committed;
+    if (left == 0 || (a.tail > 0 && left <= a.tail)) return;  // the list stays empty
+    const int set = dlist(kk);
+    const unsigned* bits = dbits(a, kk);
+    // offsets: the counts of the workgroups before this one (and, for the
+    // last workgroup, the list totals)
+    int pre[kBins];
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) pre[b] = 0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x; q += kBlock)
+#pragma unroll
+        for (int b = 0; b < kBins; ++b) pre[b] += a.bcnt[q * 8 + b];
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        const int t = group_sum<kWave>(pre[b]);
+        if (__lane_id() == 0) wsum[threadIdx.x / kWave][b] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+        int t = 0;
+        for (int q = 0; q < kWaves; ++q) t += wsum[q][threadIdx.x];
+        base[threadIdx.x] = t;
+        if (blockIdx.x == gridDim.x - 1) a.ctl->cnt[set][threadIdx.x] = t + a.bcnt[blockIdx.x * 8 + threadIdx.x];
+    }
+    __syncthreads();
+    // this thread's offsets inside the workgroup: exclusive scan of the
+    // slices' counts (waves in order, lanes in order)
+    int w0, w1;
+    compact_slice(a.nwords, &w0, &w1);
+    int c[kBins];
+    compact_count(a, bits, w0, w1, c);
+    int off[kBins];
+    const int lane = __lane_id();
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        int x = c[b];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        off[b] = x - c[b];
+        if (lane == kWave - 1) wsum[threadIdx.x / kWave][b] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        int before = base[b];
+        for (int q = 0; q < (int)threadIdx.x / kWave; ++q) before += wsum[q][b];
+        off[b] += before;
+    }
+    for (int w = w0; w < w1; ++w) {
+        const unsigned x = bits[w];
+        if (x == 0u) continue;
+#pragma unroll
+        for (int b = 0; b < kBins; ++b) {
+            unsigned y = x & bin_mask(a, w, b);
+            int* dst = list_ptr(a, set, b);
+            int o = off[b];
+            while (y) {
+                dst[o++] = w * 32 + __builtin_ctz(y);
+                y &= y - 1;
+            }
+            off[b] = o;
+        }
     }
 }
 
@@ -1686,6 +2060,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_natural(Args a, int* split) {
 // Priority order, step 1: clear colours and bin every vertex.
 __global__ __launch_bounds__(kBlock) void k_setup_bins(Args a) {
     __shared__ Stage st;
+    if (a.ctl->err) return;  // the CSR failed validation: nothing is read
     stage_init(&st);
     const int stride = gridDim.x * kBlock;
     for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
@@ -1840,6 +2215,7 @@ __global__ __launch_bounds__(kBlock) void k_validate_rows(int n, int nnz, const 
 __global__ __launch_bounds__(kBlock) void k_validate_cols(int n, const int* __restrict__ row_ptr,
                                                           const int* __restrict__ col, int need_sorted,
                                                           Ctl* ctl) {
+    if (ctl->err) return;  // row offsets already failed: rows cannot be walked
     int bad = 0;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
         const int s = row_ptr[v], e = row_ptr[v + 1];
@@ -1860,6 +2236,7 @@ __global__ __launch_bounds__(kBlock) void k_validate_cols(int n, const int* __re
 // first), so a binary search decides it.
 __global__ __launch_bounds__(kBlock) void k_validate_sym(int n, const int* __restrict__ row_ptr,
                                                          const int* __restrict__ col, Ctl* ctl) {
+    if (ctl->err) return;  // ids out of range or rows unsorted: no search
     int bad = 0;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
         const int s = row_ptr[v], e = row_ptr[v + 1];
@@ -1896,7 +2273,7 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, colp, hid, hrow, hF, act, total;
+    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, colp, hid, hrow, hF, act, total;
 };
 
 Layout layout(int32_t n, int64_t nnz) {
@@ -1912,6 +2289,8 @@ Layout layout(int32_t n, int64_t nnz) {
     L.split = off; off += align_up(vn);
     L.lists = off; off += align_up(vn * kSets * kBins);
     L.dbits = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
+    L.bplane = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
+    L.bcnt = off;  off += align_up(sizeof(int32_t) * 8 * (size_t)kCompactMaxBlocks);
     L.colp = off;  off += align_up(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     // rows of degree > kHeavyDeg: at most nnz / (kHeavyDeg + 1) of them
     const size_t nh = (size_t)(nnz > 0 ? nnz : 0) / (kHeavyDeg + 1) + 1;
@@ -1935,12 +2314,14 @@ std::vector<DeviceCache> g_dev;
 // Process-wide tuning: degree-bin limits and blocks per CU of the grids.
 int g_bins[4] = {8, 32, 128, 2048};
 int g_blocks_per_cu = 4;
-// blocks per CU of k_inc_a, (unused), k_inc_c (0: g_blocks_per_cu)
-int g_kernel_blocks[3] = {0, 0, 0};
+// blocks per CU of k_inc_a and k_inc_c (0: g_blocks_per_cu)
+int g_kernel_blocks[2] = {0, 0};
 // Most rounds a call may take (0: n + 64).  Every engine ends within n
 // rounds on valid input, so the default is never reached; a smaller cap
 // exercises the GCOLOR_EROUNDS path.
 int g_round_cap = 0;
+// Vertices left to the sequential finish (GCOLOR_SERIAL_TAIL).
+int g_serial_tail = 1024;
 
 int64_t round_limit(int64_t n) {
     std::lock_guard<std::mutex> g(g_mu);
@@ -1948,7 +2329,7 @@ int64_t round_limit(int64_t n) {
 }
 
 // Optional per-kernel timing with HIP events recorded around each launch.
-enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfIncB = 3, kProfIncC = 4, kProfFlow = 5, kProfKinds = 6 };
+enum { kProfPhase1 = 0, kProfPhase2 = 1, kProfIncA = 2, kProfLists = 3, kProfIncC = 4, kProfFlow = 5, kProfKinds = 6 };
 bool g_prof = false;
 double g_prof_ms[kProfKinds] = {};
 int64_t g_prof_launches[kProfKinds] = {};
@@ -2094,6 +2475,14 @@ int run_plain(const Args& a, int64_t limit, int grid, Launcher& L, int32_t* host
     }
 }
 
+// Round kk's dirty lists, in vertex order, from its bitmap.
+hipError_t launch_dirty_lists(const Args& a, int kk, hipStream_t st) {
+    const int G = compact_blocks(a.nwords);
+    k_dcount<<<G, kBlock, 0, st>>>(a, kk);
+    k_dwrite<<<G, kBlock, 0, st>>>(a, kk);
+    return hipGetLastError();
+}
+
 // Rounds *k, *k + 1, ... up to round `last` (inclusive, at most `limit`)
 // or the end, in batches between host checks; *done when the next round's
 // dirty list is empty (every vertex committed).  GCOLOR_EROUNDS when rounds
@@ -2108,14 +2497,23 @@ int inc_rounds(const Args& a, int64_t limit, const int* grid, Launcher& L, int32
         const int nb = std::max(0, std::min(*batch, last - k + 1));
         for (int j = 0; j < nb; ++j, ++k) {
             GC_CHECK(L(kProfIncA, [&] { k_inc_a<S><<<grid[0], kBlock, 0, st>>>(a, k); }));
-            GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid[2], kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfIncC, [&] { k_inc_c<S><<<grid[1], kBlock, 0, st>>>(a, k); }));
+            GC_CHECK(L(kProfLists, [&] { (void)launch_dirty_lists(a, k + 1, st); }));
         }
         // dirty list of the next round k: empty exactly when every vertex is committed
         GC_CHECK(hipMemcpyAsync(host, &a.ctl->cnt[dlist(k)][0], sizeof(int32_t) * kBins, hipMemcpyDeviceToHost, st));
+        if (a.tail > 0)  // with a sequential finish: the vertices left
+            GC_CHECK(hipMemcpyAsync(host + 8, &a.ctl->committed, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                    st));
         GC_CHECK(hipStreamSynchronize(st));
         *kio = k;
         if (sum_counts(host) == 0) {
             *done = true;
+            return GCOLOR_OK;
+        }
+        if (a.tail > 0 &&
+            (long long)a.n - (long long)*reinterpret_cast<const unsigned long long*>(host + 8) <= a.tail) {
+            *done = true;  // the rounds since the switch did nothing
             return GCOLOR_OK;
         }
         if (k > limit) return GCOLOR_EROUNDS;
@@ -2158,6 +2556,143 @@ __global__ __launch_bounds__(kBlock) void k_widen(int n, const int8_t* __restric
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) dst[v] = (D)src[v];
 }
 
+// ---------------------------------------------------------------------------
+// Sequential finish (section "Iterative and degree of concurrency": once
+// conflicts are few, the remaining vertices can be coloured sequentially).
+// The rounds stop when at most `tail` vertices are uncoloured; those are
+// listed, then one workgroup colours them one at a time in ascending
+// (priority, id) order, each with the smallest colour none of its neighbours
+// holds (committed colours, and colours given earlier in the finish).
+// ---------------------------------------------------------------------------
+constexpr int kTailMax = 8192;   // largest tail (LDS sort keys: 64 KiB)
+constexpr int kTailSet = 5;      // list set holding the tail (unused by the rounds)
+constexpr int kTailThreads = 1024;
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_tail_collect(Args a) {
+    const S* st = static_cast<const S*>(a.st);
+    int* list = list_ptr(a, kTailSet, 0);
+    for (int base = blockIdx.x * kBlock; base < a.n; base += gridDim.x * kBlock) {
+        const int v = base + (int)threadIdx.x;
+        const bool left = v < a.n && st[v] > 0;
+        const uint64_t m = __ballot(left);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int b = 0;
+        if (__lane_id() == leader) b = atomicAdd(&a.ctl->cnt[kTailSet][0], __popcll(m));
+        b = __shfl(b, leader);
+        if (left) {
+            list[b + __popcll(m & __lanemask_lt())] = v;
+            a.color[v] = 0;  // uncoloured until the finish reaches it
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_tail_finish(Args a) {
+    __shared__ unsigned long long keys[kTailMax];
+    __shared__ uint64_t red[kTailThreads / kWave];
+    const int m = min(a.ctl->cnt[kTailSet][0], kTailMax);
+    const int* list = list_ptr(a, kTailSet, 0);
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kTailThreads) {
+        if (i < m) {
+            const int v = list[i];
+            const uint32_t kv = a.key ? a.key[v] : (uint32_t)v;
+            keys[i] = ((unsigned long long)kv << 32) | (unsigned)v;
+        } else {
+            keys[i] = ~0ull;
+        }
+    }
+    __syncthreads();
+    // bitonic sort of (priority, id) ascending
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kTailThreads) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = keys[i], y = keys[l];
+                    if (((i & k) == 0) == (x > y)) {
+                        keys[i] = y;
+                        keys[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    constexpr int nw = kTailThreads / kWave;
+    for (int i = 0; i < m; ++i) {
+        const int v = (int)(unsigned)(keys[i] & 0xffffffffull);
+        const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+        int c = 0;
+        for (int base = 1; c == 0; base += 64) {
+            uint64_t mask = 0;
+            for (int p = s + (int)threadIdx.x; p < e; p += kTailThreads) {
+                const int w = a.colp[p];
+                const unsigned x = (unsigned)(a.color[w] - base);
+                if (w != v && x < 64u) mask |= 1ull << x;
+            }
+            mask = group_or<kWave>(mask);
+            if (__lane_id() == 0) red[threadIdx.x / kWave] = mask;
+            __syncthreads();
+            uint64_t all = 0;
+#pragma unroll
+            for (int q = 0; q < nw; ++q) all |= red[q];
+            __syncthreads();
+            if (~all) c = base + __builtin_ctzll(~all);
+        }
+        if (threadIdx.x == 0) a.color[v] = c;
+        __syncthreads();  // the colour is seen by the next vertices' scans
+    }
+    if (threadIdx.x == 0 && m > 0) atomicAdd((unsigned long long*)&a.ctl->committed, (unsigned long long)m);
+}
+
+// Stream-ordered colouring: the round count is not known to the host, so the
+// engine enqueues a fixed budget of rounds; a round whose dirty list is empty
+// finds no work and its blocks return at once.  The state widens (to int32)
+// before round 128 only when round 128 has work.
+__global__ __launch_bounds__(kBlock) void k_widen_if_busy(int n, const int8_t* __restrict__ src,
+                                                          int32_t* __restrict__ dst, const Ctl* ctl, int set) {
+    int busy = 0;
+    for (int b = 0; b < kBins; ++b) busy += ctl->cnt[set][b];
+    if (busy == 0) return;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) dst[v] = (int32_t)src[v];
+}
+
+// Device-side end of a stream-ordered colouring: the statistics of the call
+// and its status (GCOLOR_ECSR after failed validation, GCOLOR_EROUNDS when
+// the round budget ended with vertices left, GCOLOR_EINTERNAL when the
+// worklist emptied early).  One thread; the edge work sums the per-round
+// worklist degree sums, nnz minus the degrees committed in earlier rounds.
+__global__ void k_async_empty(gcolor_stats_t* out) {
+    if (threadIdx.x == 0) *out = gcolor_stats_t{0, 0, 0, GCOLOR_OK, 0};
+}
+
+__global__ void k_async_finish(const Ctl* ctl, const long long* __restrict__ log, int n, long long nnz,
+                               int next_set, gcolor_stats_t* out) {
+    if (threadIdx.x != 0) return;
+    int status = GCOLOR_OK;
+    int left = 0;
+    for (int b = 0; b < kBins; ++b) left += ctl->cnt[next_set][b];
+    if (ctl->err) status = GCOLOR_ECSR;
+    else if (ctl->committed != (unsigned long long)n) status = left ? GCOLOR_EROUNDS : GCOLOR_EINTERNAL;
+    const int rounds = ctl->rounds;
+    long long ew = 0, e = nnz;
+    const int nl = min(rounds, kMaxLog);
+    for (int r = 0; r < nl; ++r) {
+        ew += e;
+        e -= log[kLogW * r + 1];
+    }
+    gcolor_stats_t st;
+    st.rounds = status == GCOLOR_OK ? rounds : 0;
+    st.num_colors = status == GCOLOR_OK ? ctl->maxcolor : 0;
+    st.edge_work = status == GCOLOR_OK ? ew : 0;
+    st.status = status;
+    st.serial_tail = 0;
+    *out = st;
+}
+
 // A tentative colour is at most one above the largest committed colour, and
 // that grows by at most one per round, so every colour of rounds 1..127 fits
 // a signed byte: the engine starts with 8-bit state words (half the bytes of
@@ -2168,33 +2703,81 @@ int run_incremental(Args a, int64_t n, int64_t limit, int vgrid, const int* grid
     constexpr int kLast8 = 127;
     k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
-    GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid[2], kBlock, 0, st>>>(a, 1); }));
-    int k = 2, batch = 4;
-    bool done = false;
-    int rc = inc_rounds<int8_t>(a, limit, grid, L, host, st, &k, kLast8, &batch, &done);
-    if (rc) return rc;
-    if (!done) {
-        k_maxdeg<<<vgrid, kBlock, 0, st>>>((int)n, a.row_ptr, a.ctl);
-        GC_CHECK(hipGetLastError());
-        GC_CHECK(hipMemcpyAsync(host, &a.ctl->maxdeg, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GC_CHECK(hipStreamSynchronize(st));
-        const int8_t* narrow = static_cast<const int8_t*>(a.st);
-        a.st = wide_slot;
-        if (host[0] + 1 <= 32767) {
-            k_widen<int16_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int16_t*>(wide_slot));
-            GC_CHECK(hipGetLastError());
-            rc = inc_rounds<int16_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
-        } else {
-            k_widen<int32_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int32_t*>(wide_slot));
-            GC_CHECK(hipGetLastError());
-            rc = inc_rounds<int32_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
-        }
+    int width = 1;  // bytes of the state words when the rounds end
+    if (a.tail < n) {  // with a sequential finish of every vertex there is no round
+        GC_CHECK(L(kProfIncC, [&] { k_inc_c<int8_t><<<grid[1], kBlock, 0, st>>>(a, 1); }));
+        GC_CHECK(L(kProfLists, [&] { (void)launch_dirty_lists(a, 2, st); }));
+        int k = 2, batch = 4;
+        bool done = false;
+        int rc = inc_rounds<int8_t>(a, limit, grid, L, host, st, &k, kLast8, &batch, &done);
         if (rc) return rc;
+        if (!done) {
+            k_maxdeg<<<vgrid, kBlock, 0, st>>>((int)n, a.row_ptr, a.ctl);
+            GC_CHECK(hipGetLastError());
+            GC_CHECK(hipMemcpyAsync(host, &a.ctl->maxdeg, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            GC_CHECK(hipStreamSynchronize(st));
+            const int8_t* narrow = static_cast<const int8_t*>(a.st);
+            a.st = wide_slot;
+            if (host[0] + 1 <= 32767) {
+                k_widen<int16_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int16_t*>(wide_slot));
+                GC_CHECK(hipGetLastError());
+                rc = inc_rounds<int16_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+                width = 2;
+            } else {
+                k_widen<int32_t><<<vgrid, kBlock, 0, st>>>((int)n, narrow, static_cast<int32_t*>(wide_slot));
+                GC_CHECK(hipGetLastError());
+                rc = inc_rounds<int32_t>(a, limit, grid, L, host, st, &k, INT_MAX - 16, &batch, &done);
+                width = 4;
+            }
+            if (rc) return rc;
+        }
+    }
+    if (a.tail > 0) {
+        // the vertices the rounds left (at most `tail`), one at a time
+        if (width == 1) k_tail_collect<int8_t><<<vgrid, kBlock, 0, st>>>(a);
+        else if (width == 2) k_tail_collect<int16_t><<<vgrid, kBlock, 0, st>>>(a);
+        else k_tail_collect<int32_t><<<vgrid, kBlock, 0, st>>>(a);
+        k_tail_finish<<<1, kTailThreads, 0, st>>>(a);
+        GC_CHECK(hipGetLastError());
     }
     unsigned long long committed = 0;
     GC_CHECK(hipMemcpyAsync(&committed, &a.ctl->committed, sizeof(committed), hipMemcpyDeviceToHost, st));
     GC_CHECK(hipStreamSynchronize(st));
     return committed == (unsigned long long)n ? GCOLOR_OK : GCOLOR_EINTERNAL;
+}
+
+// Device arguments of one colouring: the caller's arrays and the workspace
+// carved up by its layout.
+Args make_args(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t* colors, char* base,
+               const Layout& Lw, Ctl* ctl, long long* log) {
+    Args a;
+    a.n = n;
+    a.row_ptr = row_ptr;
+    a.colp = col_idx;
+    a.split = reinterpret_cast<int*>(base + Lw.split);
+    a.color = colors;
+    a.tent = reinterpret_cast<int*>(base + Lw.tent);
+    // the incremental engine's state words share the plain engine's slots
+    a.st = base + Lw.tent;
+    a.conf = reinterpret_cast<int*>(base + Lw.conf);
+    a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
+    a.lists = reinterpret_cast<int*>(base + Lw.lists);
+    a.dbits = reinterpret_cast<unsigned*>(base + Lw.dbits);
+    a.bplane = reinterpret_cast<unsigned*>(base + Lw.bplane);
+    a.nwords = (int)(((int64_t)n + 31) / 32);
+    a.ctl = ctl;
+    a.log = log;
+    a.cfg = current_bins();
+    a.hid = reinterpret_cast<int*>(base + Lw.hid);
+    a.hrow = reinterpret_cast<int4*>(base + Lw.hrow);
+    a.hF = reinterpret_cast<unsigned*>(base + Lw.hF);
+    a.act = reinterpret_cast<int*>(base + Lw.act);
+    a.nnz = nnz;
+    a.tail = 0;
+    a.key = nullptr;
+    a.bcnt = reinterpret_cast<int*>(base + Lw.bcnt);
+
+    return a;
 }
 
 int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -2212,11 +2795,11 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     const bool plain = (flags & GCOLOR_PLAIN) != 0;
     const bool flow = (flags & GCOLOR_DATAFLOW) != 0;
     const bool natural = priority == nullptr;
-    int grid, kgrid[3];
+    int grid, kgrid[2];
     {
         std::lock_guard<std::mutex> g(g_mu);
         grid = cus * g_blocks_per_cu;
-        for (int i = 0; i < 3; ++i) kgrid[i] = cus * (g_kernel_blocks[i] > 0 ? g_kernel_blocks[i] : g_blocks_per_cu);
+        for (int i = 0; i < 2; ++i) kgrid[i] = cus * (g_kernel_blocks[i] > 0 ? g_kernel_blocks[i] : g_blocks_per_cu);
     }
 
     k_zero_ctl<<<1, 64, 0, st>>>(ctl);
@@ -2226,28 +2809,12 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         if (rc) return rc;
     }
 
-    Args a;
-    a.n = n;
-    a.row_ptr = row_ptr;
-    a.colp = col_idx;
-    a.split = reinterpret_cast<int*>(base + Lw.split);
-    a.color = colors;
-    a.tent = reinterpret_cast<int*>(base + Lw.tent);
-    // the incremental engine's state words share the plain engine's slots
-    a.st = base + Lw.tent;
-    a.conf = reinterpret_cast<int*>(base + Lw.conf);
-    a.cflag = reinterpret_cast<int*>(base + Lw.cflag);
-    a.lists = reinterpret_cast<int*>(base + Lw.lists);
-    a.dbits = reinterpret_cast<unsigned*>(base + Lw.dbits);
-    a.nwords = (int)(((int64_t)n + 31) / 32);
-    a.ctl = ctl;
-    a.log = log;
-    a.cfg = current_bins();
-    a.hid = reinterpret_cast<int*>(base + Lw.hid);
-    a.hrow = reinterpret_cast<int4*>(base + Lw.hrow);
-    a.hF = reinterpret_cast<unsigned*>(base + Lw.hF);
-    a.act = reinterpret_cast<int*>(base + Lw.act);
-    a.nnz = nnz;
+    Args a = make_args(n, nnz, row_ptr, col_idx, colors, base, Lw, ctl, log);
+    a.key = priority;
+    if (flags & GCOLOR_SERIAL_TAIL) {
+        std::lock_guard<std::mutex> g(g_mu);
+        a.tail = g_serial_tail;
+    }
 
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
     if (!natural) {
@@ -2337,7 +2904,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
             for (int r = 0; r < nl; ++r) ew += E[r];
             stats->edge_work = ew;
             stats->status = 0;
-            stats->reserved = 0;
+            stats->serial_tail = a.tail > 0 ? hc.cnt[kTailSet][0] : 0;
         }
         if (round_log) {
             for (int r = 0; r < std::min(nl, max_log); ++r) {
@@ -2351,6 +2918,71 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
             }
         }
     }
+    return GCOLOR_OK;
+}
+
+// Stream-ordered incremental colouring with a round budget (no host
+// synchronisation, no allocation).
+int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* priority,
+              int32_t* colors, void* ws, int32_t budget, bool validate, gcolor_stats_t* stats_dev, hipStream_t st) {
+    int dev = 0;
+    GC_CHECK(hipGetDevice(&dev));
+    const int cus = device_cus(dev);
+    const Layout Lw = layout(n, nnz);
+    char* base = static_cast<char*>(ws);
+    Ctl* ctl = reinterpret_cast<Ctl*>(base + Lw.ctl);
+    long long* log = reinterpret_cast<long long*>(base + Lw.log);
+    int grid, kgrid[2];
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        grid = cus * g_blocks_per_cu;
+        for (int i = 0; i < 2; ++i) kgrid[i] = cus * (g_kernel_blocks[i] > 0 ? g_kernel_blocks[i] : g_blocks_per_cu);
+    }
+    k_zero_ctl<<<1, 64, 0, st>>>(ctl);
+    GC_CHECK(hipGetLastError());
+    if (validate) {
+        // each stage returns at once when an earlier one found an error
+        k_validate_rows<<<grid, kBlock, 0, st>>>(n, (int)nnz, row_ptr, ctl);
+        k_validate_cols<<<grid, kBlock, 0, st>>>(n, row_ptr, col_idx, 1, ctl);
+        k_validate_sym<<<grid, kBlock, 0, st>>>(n, row_ptr, col_idx, ctl);
+        GC_CHECK(hipGetLastError());
+    }
+    Args a = make_args(n, nnz, row_ptr, col_idx, colors, base, Lw, ctl, log);
+    const bool natural = priority == nullptr;
+    const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    if (!natural) {
+        int* colp = reinterpret_cast<int*>(base + Lw.colp);
+        k_setup_bins<<<vgrid, kBlock, 0, st>>>(a);
+        k_reorder<<<grid, kBlock, 0, st>>>(a, col_idx, colp, a.split, priority);
+        GC_CHECK(hipGetLastError());
+        a.colp = colp;
+    }
+    constexpr int kLast8 = 127;
+    k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    k_inc_c<int8_t><<<kgrid[1], kBlock, 0, st>>>(a, 1);
+    GC_CHECK(launch_dirty_lists(a, 2, st));
+    int k = 2;
+    for (; k <= std::min(budget, kLast8); ++k) {
+        k_inc_a<int8_t><<<kgrid[0], kBlock, 0, st>>>(a, k);
+        k_inc_c<int8_t><<<kgrid[1], kBlock, 0, st>>>(a, k);
+        GC_CHECK(launch_dirty_lists(a, k + 1, st));
+    }
+    GC_CHECK(hipGetLastError());
+    if (budget > kLast8) {
+        void* wide = base + Lw.told;
+        k_widen_if_busy<<<vgrid, kBlock, 0, st>>>(n, static_cast<const int8_t*>(a.st), static_cast<int32_t*>(wide),
+                                                 ctl, dlist(kLast8 + 1));
+        a.st = wide;
+        for (; k <= budget; ++k) {
+            k_inc_a<int32_t><<<kgrid[0], kBlock, 0, st>>>(a, k);
+            k_inc_c<int32_t><<<kgrid[1], kBlock, 0, st>>>(a, k);
+            GC_CHECK(launch_dirty_lists(a, k + 1, st));
+        }
+        GC_CHECK(hipGetLastError());
+    }
+    k_maxcolor<<<grid, kBlock, 0, st>>>(n, colors, ctl);
+    k_async_finish<<<1, 64, 0, st>>>(ctl, log, n, (long long)nnz, dlist(budget + 1), stats_dev);
+    GC_CHECK(hipGetLastError());
     return GCOLOR_OK;
 }
 
@@ -2376,8 +3008,10 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, co
                    int32_t* colors_out, void* workspace, size_t ws_bytes, uint32_t flags,
                    gcolor_stats_t* stats, gcolor_round_t* round_log, int32_t max_log, gcolor_stream_t stream) {
     if (n < 0) return GCOLOR_EINVAL;
-    if (flags & ~(uint32_t)(GCOLOR_VALIDATE | GCOLOR_STATS | GCOLOR_PLAIN | GCOLOR_DATAFLOW)) return GCOLOR_EINVAL;
+    if (flags & ~(uint32_t)(GCOLOR_VALIDATE | GCOLOR_STATS | GCOLOR_PLAIN | GCOLOR_DATAFLOW | GCOLOR_SERIAL_TAIL))
+        return GCOLOR_EINVAL;
     if ((flags & GCOLOR_PLAIN) && (flags & GCOLOR_DATAFLOW)) return GCOLOR_EINVAL;
+    if ((flags & GCOLOR_SERIAL_TAIL) && (flags & (GCOLOR_PLAIN | GCOLOR_DATAFLOW))) return GCOLOR_EINVAL;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (n == 0) return GCOLOR_OK;
     if (!row_ptr || !colors_out) return GCOLOR_EINVAL;
@@ -2405,6 +3039,23 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, co
 int color_graph(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* priority,
                 int32_t* colors_out, gcolor_stream_t stream) {
     return color_graph_ex(n, row_ptr, col_idx, priority, colors_out, nullptr, 0, 0, nullptr, nullptr, 0, stream);
+}
+
+int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      const uint32_t* priority, int32_t* colors_out, void* workspace, size_t ws_bytes,
+                      int32_t max_rounds, uint32_t flags, gcolor_stats_t* stats_dev, gcolor_stream_t stream) {
+    if (n < 0 || nnz < 0 || nnz > INT_MAX || max_rounds < 1 || !stats_dev) return GCOLOR_EINVAL;
+    if (flags & ~(uint32_t)GCOLOR_VALIDATE) return GCOLOR_EINVAL;
+    if (n > 0 && (!row_ptr || !colors_out || !workspace)) return GCOLOR_EINVAL;
+    if (nnz > 0 && !col_idx) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) {
+        k_async_empty<<<1, 64, 0, st>>>(stats_dev);
+        return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+    }
+    if (ws_bytes < gcolor_workspace_bytes(n, nnz)) return GCOLOR_EWORKSPACE;
+    return run_async(n, nnz, row_ptr, col_idx, priority, colors_out, workspace, max_rounds,
+                     (flags & GCOLOR_VALIDATE) != 0, stats_dev, st);
 }
 
 const char* gcolor_strerror(int code) {
@@ -2436,20 +3087,32 @@ int gcolor_set_tuning(const int32_t* bin_limits, int32_t blocks_per_cu) {
     return GCOLOR_OK;
 }
 
-int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_b, int32_t blocks_c) {
-    const int32_t v[3] = {blocks_a, blocks_b, blocks_c};
-    for (int i = 0; i < 3; ++i)
-        if (v[i] < 0 || v[i] > 64) return GCOLOR_EINVAL;
+int gcolor_set_kernel_blocks(int32_t blocks_a, int32_t blocks_c) {
+    if (blocks_a < 0 || blocks_a > 64 || blocks_c < 0 || blocks_c > 64) return GCOLOR_EINVAL;
     std::lock_guard<std::mutex> g(g_mu);
-    for (int i = 0; i < 3; ++i) g_kernel_blocks[i] = v[i];
+    g_kernel_blocks[0] = blocks_a;
+    g_kernel_blocks[1] = blocks_c;
     return GCOLOR_OK;
 }
 
-int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_b, int32_t* blocks_c) {
+int gcolor_get_kernel_blocks(int32_t* blocks_a, int32_t* blocks_c) {
     std::lock_guard<std::mutex> g(g_mu);
     if (blocks_a) *blocks_a = g_kernel_blocks[0];
-    if (blocks_b) *blocks_b = g_kernel_blocks[1];
-    if (blocks_c) *blocks_c = g_kernel_blocks[2];
+    if (blocks_c) *blocks_c = g_kernel_blocks[1];
+    return GCOLOR_OK;
+}
+
+int gcolor_set_serial_tail(int32_t max_vertices) {
+    if (max_vertices < 1 || max_vertices > kTailMax) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_serial_tail = max_vertices;
+    return GCOLOR_OK;
+}
+
+int gcolor_get_serial_tail(int32_t* max_vertices) {
+    if (!max_vertices) return GCOLOR_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    *max_vertices = g_serial_tail;
     return GCOLOR_OK;
 }
 

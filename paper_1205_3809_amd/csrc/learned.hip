@@ -678,6 +678,27 @@ __global__ __launch_bounds__(256) void k_refresh_bf16(const float* __restrict__ 
     for (int p = blockIdx.x * 256 + threadIdx.x; p < kNP; p += gridDim.x * 256) wbf[p] = f32_to_bf16(master[p]);
 }
 
+// Normalisation from the sums of k_feat_stats over `count` vertices: per
+// feature the mean and the population standard deviation of log1p(feature),
+// the variance floored at 1e-12 (a constant feature keeps a finite scale).
+__global__ void k_feat_norm(int64_t count, const double* __restrict__ acc, float* __restrict__ norm) {
+    const int f = threadIdx.x;
+    if (f >= kF) return;
+    const double c = (double)count;
+    const double mean = acc[f] / c;
+    const double var = fmax(acc[kF + f] / c - mean * mean, 1e-12);
+    norm[f] = (float)mean;
+    norm[kF + f] = (float)sqrt(var);
+}
+
+// Training target of smallest-last position r among n vertices:
+// log(1 + r) / log(max(n, 2)), in [0, 1] and increasing in r.
+__global__ __launch_bounds__(256) void k_rank_targets(int n, const int* __restrict__ rank, float* __restrict__ target) {
+    const double inv = 1.0 / log((double)max(n, 2));
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256)
+        target[v] = (float)(log1p((double)rank[v]) * inv);
+}
+
 // Order-preserving map of float scores to uint32 keys: flip all bits of a
 // negative float, flip only the sign bit of a non-negative one.  NaN scores
 // are reported through *bad.
@@ -693,35 +714,6 @@ __global__ __launch_bounds__(256) void k_score_keys(int64_t n, const float* __re
 
 // Per-device buffer for the heavy-vertex list of gcolor_features: a count
 // (padded to 256 bytes) and up to n vertex ids; grown on demand.
-struct HeavyBuf {
-    int* p = nullptr;
-    int64_t cap = 0;
-};
-std::mutex g_heavy_mu;
-std::vector<HeavyBuf> g_heavy;
-
-hipError_t heavy_buffer(int n, int** out) {
-    int dev = 0;
-    hipError_t rc = hipGetDevice(&dev);
-    if (rc != hipSuccess) return rc;
-    std::lock_guard<std::mutex> g(g_heavy_mu);
-    if ((int)g_heavy.size() <= dev) g_heavy.resize(dev + 1);
-    HeavyBuf& b = g_heavy[dev];
-    if (b.cap < n) {
-        if (b.p) {
-            rc = hipFree(b.p);
-            b.p = nullptr;
-            b.cap = 0;
-            if (rc != hipSuccess) return rc;
-        }
-        rc = hipMalloc((void**)&b.p, ((size_t)n + 64) * sizeof(int));
-        if (rc != hipSuccess) return rc;
-        b.cap = n;
-    }
-    *out = b.p;
-    return hipSuccess;
-}
-
 int grid_for(int64_t items, int per_block) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -781,16 +773,20 @@ int32_t smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col
 
 extern "C" {
 
+size_t gcolor_features_workspace_bytes(int32_t n) {
+    if (n < 0) return 0;
+    return ((size_t)n + 64) * sizeof(int);
+}
+
 int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
-                    gcolor_stream_t stream) {
+                    void* workspace, size_t ws_bytes, gcolor_stream_t stream) {
     if (n < 0) return GCOLOR_EINVAL;
     if (n == 0) return GCOLOR_OK;
-    if (!row_ptr || !feat_out) return GCOLOR_EINVAL;
+    if (!row_ptr || !feat_out || !workspace) return GCOLOR_EINVAL;
+    if (ws_bytes < gcolor_features_workspace_bytes(n)) return GCOLOR_EWORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    int* buf = nullptr;
-    if (heavy_buffer(n, &buf) != hipSuccess) return GCOLOR_EHIP;
-    int* count = buf;
-    int* list = buf + 64;
+    int* count = static_cast<int*>(workspace);
+    int* list = count + 64;
     k_zero_count<<<1, 64, 0, st>>>(count);
     k_features<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, seed, feat_out, list, count);
     // one workgroup per listed vertex (grid-strided over the device count)
@@ -860,6 +856,49 @@ int gcolor_scores_to_keys(int64_t n, const float* score, uint32_t* keys, int32_t
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     k_score_keys<<<grid_for(n, 256), 256, 0, st>>>(n, score, keys, bad);
     return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_feature_norm(int64_t count, const double* acc, float* norm, gcolor_stream_t stream) {
+    if (count <= 0 || !acc || !norm) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_feat_norm<<<1, 64, 0, st>>>(count, acc, norm);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+int gcolor_rank_targets(int32_t n, const int32_t* rank, float* target, gcolor_stream_t stream) {
+    if (n < 0) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    if (!rank || !target) return GCOLOR_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    k_rank_targets<<<grid_for(n, 256), 256, 0, st>>>(n, rank, target);
+    return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
+}
+
+size_t gcolor_order_learned_workspace_bytes(int32_t n) {
+    if (n < 0) return 0;
+    const size_t feat = (((size_t)n * kF * sizeof(float)) + 255) & ~(size_t)255;
+    const size_t score = (((size_t)n * sizeof(float)) + 255) & ~(size_t)255;
+    return feat + score + gcolor_features_workspace_bytes(n);
+}
+
+int gcolor_order_learned(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed,
+                         const float* master, const uint16_t* wbf, const float* norm, uint32_t* keys_out,
+                         int32_t* nan_flag, void* workspace, size_t ws_bytes, gcolor_stream_t stream) {
+    if (n < 0 || !master || !wbf || !norm || !nan_flag) return GCOLOR_EINVAL;
+    if (n == 0) return GCOLOR_OK;
+    if (!row_ptr || !keys_out || !workspace) return GCOLOR_EINVAL;
+    if (ws_bytes < gcolor_order_learned_workspace_bytes(n)) return GCOLOR_EWORKSPACE;
+    char* base = static_cast<char*>(workspace);
+    float* feat = reinterpret_cast<float*>(base);
+    const size_t fb = (((size_t)n * kF * sizeof(float)) + 255) & ~(size_t)255;
+    float* score = reinterpret_cast<float*>(base + fb);
+    const size_t sb = (((size_t)n * sizeof(float)) + 255) & ~(size_t)255;
+    void* fws = base + fb + sb;
+    int rc = gcolor_features(n, row_ptr, col_idx, seed, feat, fws, gcolor_features_workspace_bytes(n), stream);
+    if (rc) return rc;
+    rc = gcolor_mlp_forward(n, feat, master, wbf, norm, score, stream);
+    if (rc) return rc;
+    return gcolor_scores_to_keys(n, score, keys_out, nan_flag, stream);
 }
 
 int gcolor_smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* rank,

@@ -4,7 +4,7 @@ Every numeric step runs in libgcolor.so kernels (features, forward, gradient,
 Adam, score-to-key map, colouring); this module only schedules them:
 
 * targets: exact smallest-last positions from the library's host routine,
-  as log(1 + rank) / log(n) (0 = coloured first);
+  mapped on the device to log(1 + rank) / log(n) (0 = coloured first);
 * training: minibatches of vertices drawn (seeded) across the training
   graphs, mean squared error, Adam on FP32 master weights, BF16 copies for
   the forward pass;
@@ -46,7 +46,10 @@ def _stream():
 def features(row_ptr: torch.Tensor, col_idx: torch.Tensor, seed: int = 0x5EED) -> torch.Tensor:
     n = row_ptr.numel() - 1
     out = torch.empty((max(n, 0), NF), dtype=torch.float32, device=row_ptr.device)
-    _check(B._lib.gcolor_features(n, _vp(row_ptr), _vp(col_idx), seed, _vp(out), _stream()), "gcolor_features")
+    nb = int(B._lib.gcolor_features_workspace_bytes(max(n, 0)))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=row_ptr.device)
+    _check(B._lib.gcolor_features(n, _vp(row_ptr), _vp(col_idx), seed, _vp(out), _vp(ws), nb, _stream()),
+           "gcolor_features")
     return out
 
 
@@ -88,15 +91,16 @@ class MLP:
         _check(B._lib.gcolor_mlp_refresh_bf16(_vp(self.master), _vp(self.wbf), _stream()), "refresh_bf16")
 
     def fit_norm(self, feats: Sequence[torch.Tensor]):
+        """Per-feature mean and standard deviation of log1p(feature) over the
+        vertices of every tensor in feats (library kernels)."""
         acc = torch.zeros(2 * NF, dtype=torch.float64, device=self.device)
         total = 0
         for f in feats:
             _check(B._lib.gcolor_feature_stats(f.shape[0], _vp(f), _vp(acc), _stream()), "feature_stats")
             total += f.shape[0]
-        a = acc.cpu().numpy()
-        mean = a[:NF] / total
-        var = np.maximum(a[NF:] / total - mean * mean, 1e-12)
-        self.norm = torch.from_numpy(np.r_[mean, np.sqrt(var)].astype(np.float32)).to(self.device)
+        norm = torch.empty(2 * NF, dtype=torch.float32, device=self.device)
+        _check(B._lib.gcolor_feature_norm(total, _vp(acc), _vp(norm), _stream()), "feature_norm")
+        self.norm = norm
 
     def scores(self, feat: torch.Tensor) -> torch.Tensor:
         out = torch.empty(feat.shape[0], dtype=torch.float32, device=self.device)
@@ -142,14 +146,15 @@ class TrainReport(NamedTuple):
     vertices: int
 
 
-def rank_target(rank: np.ndarray) -> np.ndarray:
-    """Training target for smallest-last position r of n: log(1 + r) / log(n),
-    in [0, 1] and monotone in r.  The log scale spreads out the head of the
-    order (the dense core, coloured first), where the colour count is
-    decided; a plain r / (n - 1) target lets the many low-degree vertices
-    dominate the squared error."""
-    n = rank.shape[0]
-    return (np.log1p(rank.astype(np.float64)) / np.log(max(n, 2))).astype(np.float32)
+def rank_targets(rank: torch.Tensor) -> torch.Tensor:
+    """Training targets of smallest-last positions r of n (device int32):
+    log(1 + r) / log(n), in [0, 1] and monotone in r (library kernel).  The
+    log scale spreads out the head of the order (the dense core, coloured
+    first), where the colour count is decided; a plain r / (n - 1) target
+    lets the many low-degree vertices dominate the squared error."""
+    out = torch.empty(rank.numel(), dtype=torch.float32, device=rank.device)
+    _check(B._lib.gcolor_rank_targets(rank.numel(), _vp(rank), _vp(out), _stream()), "rank_targets")
+    return out
 
 
 def train(model: MLP, graphs, epochs: int = 3, batch: int = 65536, lr: float = 2e-3, seed: int = 7,
@@ -163,7 +168,7 @@ def train(model: MLP, graphs, epochs: int = 3, batch: int = 65536, lr: float = 2
         cid = torch.from_numpy(np.ascontiguousarray(ci)).to(dev)
         feats.append(features(rpd, cid, feat_seed))
         rank, _ = smallest_last_rank(rp, ci)
-        targs.append(torch.from_numpy(rank_target(rank)).to(dev))
+        targs.append(rank_targets(torch.from_numpy(rank).to(dev)))
     model.fit_norm(feats)
     F = torch.cat(feats, 0)
     T = torch.cat(targs, 0)
@@ -198,10 +203,16 @@ def keys_from_scores(scores: torch.Tensor) -> torch.Tensor:
 
 
 def order_learned(model: MLP, row_ptr: torch.Tensor, col_idx: torch.Tensor, feat_seed: int = 0x5EED):
-    """Priority keys (int32 bit patterns of uint32) for color_graph."""
-    f = features(row_ptr, col_idx, feat_seed)
-    s = model.scores(f)
-    keys, bad = keys_from_scores(s)
+    """Priority keys (int32 bit patterns of uint32) for color_graph, from one
+    library call (features, MLP forward, key map); also the NaN flag."""
+    n = row_ptr.numel() - 1
+    keys = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    bad = torch.zeros(1, dtype=torch.int32, device=row_ptr.device)
+    nb = int(B._lib.gcolor_order_learned_workspace_bytes(max(n, 0)))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=row_ptr.device)
+    _check(B._lib.gcolor_order_learned(n, _vp(row_ptr), _vp(col_idx), feat_seed, _vp(model.master), _vp(model.wbf),
+                                       _vp(model.norm), _vp(keys), _vp(bad), _vp(ws), nb, _stream()),
+           "gcolor_order_learned")
     return keys, bad
 
 

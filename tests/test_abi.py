@@ -83,6 +83,27 @@ def test_argument_errors_before_any_device_work():
     assert lib.color_graph(5, None, fake, None, fake, None) == -1
     assert lib.color_graph(5, fake, fake, None, None, None) == -1
     assert lib.color_graph_ex(5, fake, fake, None, fake, None, 0, 1 << 20, None, None, 0, None) == -1
+    # stream-ordered entry: negative sizes, no budget, no stats, unknown flags,
+    # NULL arrays, nnz beyond int32, a short workspace
+    A = lib.color_graph_async
+    need = gc.workspace_bytes(5, 8)
+    assert A(-1, 8, fake, fake, None, fake, fake, need, 10, 0, fake, None) == -1
+    assert A(5, -1, fake, fake, None, fake, fake, need, 10, 0, fake, None) == -1
+    assert A(5, 8, fake, fake, None, fake, fake, need, 0, 0, fake, None) == -1
+    assert A(5, 8, fake, fake, None, fake, fake, need, 10, 0, None, None) == -1
+    assert A(5, 8, fake, fake, None, fake, fake, need, 10, 4, fake, None) == -1
+    assert A(5, 8, None, fake, None, fake, fake, need, 10, 0, fake, None) == -1
+    assert A(5, 8, fake, None, None, fake, fake, need, 10, 0, fake, None) == -1
+    assert A(5, 8, fake, fake, None, fake, None, need, 10, 0, fake, None) == -1
+    assert A(5, 1 << 31, fake, fake, None, fake, fake, need, 10, 0, fake, None) == -1
+    assert A(5, 8, fake, fake, None, fake, fake, need - 1, 10, 0, fake, None) == -3
+    # learned-ordering entry points: short workspaces and bad sizes
+    assert lib.gcolor_features(5, fake, fake, 1, fake, fake, 0, None) == -3
+    assert lib.gcolor_features(5, fake, fake, 1, fake, None, 1 << 20, None) == -1
+    assert lib.gcolor_order_learned(5, fake, fake, 1, fake, fake, fake, fake, fake, fake, 0, None) == -3
+    assert lib.gcolor_order_learned(5, fake, fake, 1, fake, fake, fake, fake, None, fake, 1 << 20, None) == -1
+    assert lib.gcolor_feature_norm(0, fake, fake, None) == -1
+    assert lib.gcolor_rank_targets(-1, fake, fake, None) == -1
 
 
 def test_tuning_validation():
@@ -96,6 +117,21 @@ def test_tuning_validation():
     assert gc.get_tuning() == ([4, 16, 64, 1024], 4)
     gc.set_tuning(old, bpc)
     assert gc.get_tuning() == (old, bpc)
+
+
+def test_serial_tail_roundtrip_and_range():
+    import paper_1205_3809_amd as gc
+    old = gc.get_serial_tail()
+    try:
+        gc.set_serial_tail(8192)
+        assert gc.get_serial_tail() == 8192
+        for bad in (0, -1, 8193):
+            with pytest.raises(gc.GColorError) as e:
+                gc.set_serial_tail(bad)
+            assert e.value.code == -1
+        assert gc.get_serial_tail() == 8192
+    finally:
+        gc.set_serial_tail(old)
 
 
 def test_round_cap_roundtrip_and_range():

@@ -30,7 +30,7 @@ def gpu_blocks(g, key=None, block=64, workspace=None):
 
 def check(g, key=None, block=64, label=""):
     print("case %s n=%d nnz=%d block=%d key=%s" % (label, g.n, g.nnz, block, key is not None), flush=True)
-    ref = oracle.block_gs(g.row_ptr, g.col_idx, key, block)
+    ref = oracle.block_gs(g.row_ptr, g.col_idx, key, block, threads=0)
     col, st = gpu_blocks(g, key, block)
     mism = np.flatnonzero(col != ref.colors)
     assert mism.size == 0, "%s: %d mismatches, first at %s" % (label, mism.size, mism[:5])
@@ -162,20 +162,18 @@ def test_rmat_scale24_perm_every_vertex():
     check(g, graphgen.random_priority(g.n, 12), 64, "rmat24-perm")
 
 
-def test_rmat_scale24_natural_properties():
-    """The same graph in natural order, 64-vertex blocks: a proper colouring
-    with colour(v) <= deg(v) + 1, identical on a second call, its statistics
-    consistent with the colours.  (The oracle needs over a minute on one core
-    here; the vertex-by-vertex comparison in natural order runs at scale 20.)"""
+def test_rmat_scale24_natural_every_vertex():
+    """The same graph in natural order, 64-vertex blocks (the benchmark's
+    launch): every colour, the rounds and the edge work equal the block
+    oracle's (run on every host thread; its result does not depend on the
+    thread count); the colouring is also proper with colour(v) <= deg(v) + 1
+    and identical on a second call."""
     g = rmat24()
-    print("case rmat24-natural properties n=%d nnz=%d" % (g.n, g.nnz), flush=True)
-    col, st = gpu_blocks(g, None, 64)
+    col, st = check(g, None, 64, "rmat24-natural")
     deg = np.diff(g.row_ptr.astype(np.int64))
     assert col.min() >= 1 and np.all(col <= deg + 1)
     src = np.repeat(np.arange(g.n, dtype=np.int32), deg)
     keep = src != g.col_idx
     assert not np.any(col[src[keep]] == col[g.col_idx[keep]])
-    assert st.num_colors == int(col.max())
-    assert 1 <= st.rounds <= g.n and st.edge_work >= g.nnz
     col2, st2 = gpu_blocks(g, None, 64)
     assert np.array_equal(col, col2) and (st2.rounds, st2.edge_work) == (st.rounds, st.edge_work)

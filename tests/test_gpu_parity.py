@@ -249,9 +249,9 @@ def test_result_independent_of_tuning(engine):
     old, bpc = gc.get_tuning()
     kold = gc.get_kernel_blocks()
     try:
-        for bins, b, kb in [([0, 0, 0, 0], 2, (0, 0, 0)), ([1, 2, 3, 4], 1, (1, 16, 3)),
-                            ([64, 64, 64, 64], 16, (0, 0, 0)), ([2, 8, 64, 256], 8, (12, 2, 0)),
-                            ([1000000] * 4, 3, (0, 0, 0))]:
+        for bins, b, kb in [([0, 0, 0, 0], 2, (0, 0)), ([1, 2, 3, 4], 1, (1, 3)),
+                            ([64, 64, 64, 64], 16, (0, 0)), ([2, 8, 64, 256], 8, (12, 0)),
+                            ([1000000] * 4, 3, (0, 16))]:
             gc.set_tuning(bins, b)
             gc.set_kernel_blocks(*kb)
             got, _ = gpu_color(g, key, flags=engine)
