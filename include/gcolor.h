@@ -181,6 +181,27 @@ int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
                       int32_t max_rounds, uint32_t flags, gcolor_stats_t* stats_dev, gcolor_stream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * color_graph_async with the library's own fixed workspace, a device array
+ * of gcolor_noalloc_max_bytes() bytes (64 MiB) that is part of the code
+ * object, one per device, held until the process ends.  The call allocates
+ * nothing (the array's device address is looked up once per device, on the
+ * first call there); the caller still passes inputs and outputs as for
+ * color_graph_async.  Graphs whose gcolor_workspace_bytes(n, nnz) exceeds the
+ * array are refused with GCOLOR_ENOTSUP before any device work (about
+ * 230,000 vertices at 10 entries per vertex).  Every call on a device shares
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (other streams or threads) race and must be
+ * serialised by the caller.  Other errors and stats_dev: as
+ * color_graph_async.
+ */
+size_t gcolor_noalloc_max_bytes(void);
+int color_graph_async_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              const uint32_t* priority, int32_t* colors_out, int32_t max_rounds, uint32_t flags,
+                              gcolor_stats_t* stats_dev, gcolor_stream_t stream);
+
+/*
  * Tuning (process-wide, applies to later calls): bin_limits[4] are the
  * largest degrees of bins 0..3 (one lane, 4 lanes, 16 lanes and one
  * wavefront per vertex); larger degrees take a workgroup per vertex.  Must be

@@ -2995,6 +2995,38 @@ int read_nnz(int32_t n, const int32_t* row_ptr, hipStream_t st, int64_t* nnz) {
     return GCOLOR_OK;
 }
 
+// Workspace of the allocation-free entry point: one array per device, part
+// of the code object (so it exists on every device the library runs on and
+// is held until the process ends).  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, looked
+// up once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+
+struct ScratchAddr {
+    void* p = nullptr;
+};
+std::vector<ScratchAddr> g_scratch;  // per device, under g_mu
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GCOLOR_EHIP;
+    std::lock_guard<std::mutex> g(g_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+    if (!g_scratch[dev].p) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GCOLOR_EHIP;
+        g_scratch[dev].p = p;
+    }
+    *out = g_scratch[dev].p;
+    return GCOLOR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3056,6 +3088,25 @@ int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
     if (ws_bytes < gcolor_workspace_bytes(n, nnz)) return GCOLOR_EWORKSPACE;
     return run_async(n, nnz, row_ptr, col_idx, priority, colors_out, workspace, max_rounds,
                      (flags & GCOLOR_VALIDATE) != 0, stats_dev, st);
+}
+
+size_t gcolor_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int color_graph_async_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              const uint32_t* priority, int32_t* colors_out, int32_t max_rounds, uint32_t flags,
+                              gcolor_stats_t* stats_dev, gcolor_stream_t stream) {
+    if (n < 0 || nnz < 0 || nnz > INT_MAX || max_rounds < 1 || !stats_dev) return GCOLOR_EINVAL;
+    if (flags & ~(uint32_t)GCOLOR_VALIDATE) return GCOLOR_EINVAL;
+    if (n > 0 && (!row_ptr || !colors_out)) return GCOLOR_EINVAL;
+    if (nnz > 0 && !col_idx) return GCOLOR_EINVAL;
+    if (gcolor_workspace_bytes(n, nnz) > kScratchBytes) return GCOLOR_ENOTSUP;
+    void* ws = nullptr;
+    if (n > 0) {
+        const int rc = scratch_address(&ws);
+        if (rc) return rc;
+    }
+    return color_graph_async(n, nnz, row_ptr, col_idx, priority, colors_out, ws, kScratchBytes, max_rounds, flags,
+                             stats_dev, stream);
 }
 
 const char* gcolor_strerror(int code) {
