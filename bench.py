@@ -319,6 +319,9 @@ def main():
                     help="dataflow: the dataflow algorithm in rounds (a different colouring: the serial "
                          "greedy's); blocks: the block Gauss-Seidel variant (a different colouring)")
     ap.add_argument("--block-size", type=int, default=64, help="vertices per block of --engine blocks")
+    ap.add_argument("--serial-tail", type=int, default=0,
+                    help="incremental engine with the sequential finish: rounds while more than this many "
+                         "vertices are uncoloured, then one at a time (a different colouring; 0 = off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--autotune", action="store_true",
@@ -361,6 +364,12 @@ def main():
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     flags = {"plain": gc.FLAG_PLAIN, "dataflow": gc.FLAG_DATAFLOW}.get(args.engine, 0)
+    if args.serial_tail:
+        if args.engine != "incremental":
+            print("bench.py: --serial-tail applies to the incremental engine", file=sys.stderr)
+            sys.exit(2)
+        gc.set_serial_tail(args.serial_tail)
+        flags |= gc.FLAG_SERIAL_TAIL
     tuning = apply_tuning(args, "%s-%s%s" % (args.workload, args.order,
                                              "-dataflow" if args.engine == "dataflow" else ""),
                           lambda: gc.autotune.tune_single(rp, ci, pr, log=log, flags=flags))
@@ -535,6 +544,17 @@ def main():
         cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
                "sample": "the full workload (%.1f s)" % dt}
         log("dataflow oracle %.1fs parity=%s rounds=%d" % (dt, parity, ref.rounds))
+    elif not args.no_cpu_baseline and args.serial_tail:
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.spec_tail(g.row_ptr, g.col_idx, key, args.serial_tail)
+        dt = time.perf_counter() - t
+        parity = bool(np.array_equal(ref.colors, gpu_colors)) and ref.rounds == st.rounds
+        greedy_colors = int(oracle.greedy(g.row_ptr, g.col_idx, key).max())
+        cpu = {"value": round(g.edges / dt, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload (%.1f s)" % dt}
+        log("sequential-finish oracle %.1fs parity=%s rounds=%d finished one at a time=%d"
+            % (dt, parity, ref.rounds, ref.tail))
     elif not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
@@ -551,6 +571,8 @@ def main():
     p = WORKLOADS[args.workload][1]
     config = {"workload": "%s-%s" % (args.workload, args.order), "engine": args.engine,
               "n": g.n, "nnz": g.nnz, "edges": g.edges, "tuning": tuning}
+    if args.serial_tail:
+        config["serial_tail"] = args.serial_tail
     config.update({k: v for k, v in p.items()})
     res = {
         "metric": "edges colored/sec + % HBM peak at R-MAT s24; colors vs serial greedy",

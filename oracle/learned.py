@@ -14,8 +14,13 @@ Features of vertex v (d = degree, N(v) its neighbours):
              output mix `mix` and G = 0x9E3779B97F4A7C15, and takes row
              positions a = (h mod 2^32) mod d, b = (h div 2^32) mod (d - 1),
              b + 1 if b >= a
-  7          h-index of the neighbour degrees: largest h such that at least
-             h neighbours have degree >= h
+  7          core estimate: the H operator (Lu, Zhou, Zhang and Stanley,
+             "The H-index of a network node and its relation to degree and
+             coreness", Nature Communications 2016) applied CORE_STEPS
+             times to the degrees, where H maps values x to the h-index of
+             the neighbours' values (largest h such that at least h
+             neighbours w have x(w) >= h); one step is the h-index of the
+             neighbour degrees, and the iteration falls to the coreness
 MLP: x = (log1p(f) - mean) / std, y = W3 relu(W2 relu(W1 x + b1) + b2) + b3.
 Normalisation: mean and population standard deviation of log1p(f) per
 feature over the training vertices (variance floored at 1e-12).
@@ -30,6 +35,7 @@ from __future__ import annotations
 import numpy as np
 
 NF, NH, NPARAM = 8, 64, 4801
+CORE_STEPS = 4
 W1, B1, W2, B2, W3, B3 = 0, 512, 576, 4672, 4736, 4800
 GAMMA = 0x9E3779B97F4A7C15
 M64 = (1 << 64) - 1
@@ -64,7 +70,33 @@ def wedge_positions(v, d, i, seed):
     return a.astype(np.int64), b.astype(np.int64)
 
 
-def features(row_ptr, col_idx, seed: int = 0x5EED) -> np.ndarray:
+def h_operator(row_ptr, col_idx, x) -> np.ndarray:
+    """One application of H: for every vertex v, the largest h such that at
+    least h neighbours w have x[w] >= h (0 without neighbours).  Sorting each
+    row's neighbour values in descending order, h counts the 1-based
+    positions p whose value is >= p."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col_idx, dtype=np.int64)
+    n = row_ptr.shape[0] - 1
+    if col.size == 0:
+        return np.zeros(n, dtype=np.int64)
+    deg = np.diff(row_ptr)
+    src = np.repeat(np.arange(n), deg)
+    nv = np.asarray(x, dtype=np.int64)[col]
+    order = np.lexsort((-nv, src))
+    pos = np.arange(col.size) - row_ptr[src[order]] + 1
+    return np.bincount(src[order], weights=(nv[order] >= pos).astype(np.float64), minlength=n).astype(np.int64)
+
+
+def core_estimate(row_ptr, col_idx, steps: int = CORE_STEPS) -> np.ndarray:
+    """H applied `steps` times to the degrees (steps = 0: the degrees)."""
+    h = np.diff(np.asarray(row_ptr, dtype=np.int64))
+    for _ in range(steps):
+        h = h_operator(row_ptr, col_idx, h)
+    return h
+
+
+def features(row_ptr, col_idx, seed: int = 0x5EED, core_steps: int = CORE_STEPS) -> np.ndarray:
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col_idx, dtype=np.int64)
     n = row_ptr.shape[0] - 1
@@ -82,13 +114,7 @@ def features(row_ptr, col_idx, seed: int = 0x5EED) -> np.ndarray:
         s = np.add.reduceat(nd, starts)
         F[has, 3] = s / deg[has]
         F[has, 5] = s - deg[has]
-    # h-index: sort each row's neighbour degrees descending; count positions
-    # p (1-based) with sorted degree >= p
-    if col.size:
-        order = np.lexsort((-nd, src))
-        sd = nd[order]
-        pos = np.arange(col.size) - row_ptr[src[order]] + 1
-        F[:, 7] = np.bincount(src[order], weights=(sd >= pos).astype(np.float64), minlength=n)
+    F[:, 7] = core_estimate(row_ptr, col, core_steps)
     # wedges
     cand = np.flatnonzero(deg >= 2)
     if cand.size:

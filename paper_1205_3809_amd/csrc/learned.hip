@@ -73,13 +73,15 @@ __device__ __forceinline__ bool has_edge(const int* __restrict__ row_ptr, const 
 //  2 min neighbour degree   3 mean neighbour degree   4 max neighbour degree
 //  5 two-hop paths: sum over neighbours of (degree - 1)
 //  6 triangle estimate: closed fraction of 8 hashed wedges * deg (deg-1) / 2
-//  7 core estimate: h-index of the neighbour degrees
+//  7 core estimate: kCoreSteps applications of the H operator to the
+//    degrees (the first is the h-index of the neighbour degrees)
 //
 // Vertices below kFeatHeavy neighbours take a group of 8 lanes; the others
 // are appended to a list and take a whole workgroup each (k_features_heavy),
 // so that one hub row does not serialise the launch.
 constexpr int kFeatHeavy = 128;
 constexpr int kHistBins = 4096;
+
 
 __device__ __forceinline__ uint64_t wedge_hash(uint64_t seed, int v, int i) {
     return mix64(seed * 0x9E3779B97F4A7C15ULL + mix64((uint64_t)v * 8ULL + (uint64_t)i + 1ULL));
@@ -114,6 +116,25 @@ __device__ __forceinline__ void write_features(float* __restrict__ out, int v, i
 
 // One vertex of degree < kFeatHeavy per group of GS lanes; the neighbour
 // degrees (at most kFeatHeavy / GS per lane) stay in registers.
+// h-index of the values a group of GS lanes holds (kPer each, -1 for
+// absent entries): the largest h with at least h values >= h.  h is at most
+// cap (the count and the largest value); binary search over [0, cap].
+template <int GS, int kPer>
+__device__ __forceinline__ int group_h_index(const int (&x)[kPer], int cap) {
+    int lo = 0, hi = cap;
+    while (lo < hi) {
+        const int h = (lo + hi + 1) >> 1;
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) c += x[j] >= h;
+#pragma unroll
+        for (int o = GS / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, GS);
+        if (c >= h) lo = h;
+        else hi = h - 1;
+    }
+    return lo;
+}
+
 template <int GS>
 __device__ void features_light(int v, int s, int e, int lig, const int* __restrict__ row_ptr,
                                const int* __restrict__ col, uint64_t seed, float* __restrict__ out) {
@@ -142,20 +163,7 @@ __device__ void features_light(int v, int s, int e, int lig, const int* __restri
         mx = max(mx, __shfl_xor(mx, o, GS));
         sum += __shfl_xor(sum, o, GS);
     }
-    // h-index: largest h with at least h neighbours of degree >= h; h is at
-    // most min(d, max neighbour degree); binary search over that range
-    // (absent entries hold -1 and never count)
-    int lo = 0, hi = min(d, mx);
-    while (lo < hi) {
-        const int h = (lo + hi + 1) >> 1;
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) c += dv[j] >= h;
-#pragma unroll
-        for (int o = GS / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, GS);
-        if (c >= h) lo = h;
-        else hi = h - 1;
-    }
+    const int lo = group_h_index<GS, kPer>(dv, min(d, mx));
     int closed = 0;
     if (d >= 2)
         for (int i = lig; i < kWedges; i += GS) closed += wedge_closed(row_ptr, col, v, s, d, i, seed);
@@ -223,13 +231,63 @@ __device__ int block_max(HeavyLds* L, int x) {
     return r;
 }
 
+// h-index of the values val(col[p]) over the row [s, e), by a workgroup of
+// 256 threads, with cap >= the answer (the row length and the largest value
+// bound it).  It lies in [lo, hi] with f(lo) >= lo, where f(k) = number of
+// entries with value >= k.  One pass over the row histograms the (clamped)
+// values in [lo, hi] into at most kHistBins buckets of width W; the largest
+// bucket start k with f(k) >= k narrows the range to that bucket, and width 1
+// gives h exactly (at most three passes for any 32-bit value, one when the
+// range is below kHistBins).  Every thread returns h.
+template <class Val>
+__device__ int block_h_index(HeavyLds* L, const int* __restrict__ col, int s, int e, int cap, Val val) {
+    const int tid = threadIdx.x;
+    int lo = 0, hi = cap;
+    for (;;) {
+        const int span = hi - lo + 1;
+        const int W = (span + kHistBins - 1) / kHistBins;
+        const int nb = (span + W - 1) / W;
+        for (int j = tid; j < nb; j += 256) L->hist[j] = 0;
+        __syncthreads();
+        int above = 0;
+        for (int p = s + tid; p < e; p += 256) {
+            const int c = min(val(col[p]), cap);
+            if (c > hi) ++above;
+            else if (c >= lo) atomicAdd(&L->hist[(c - lo) / W], 1);
+        }
+        above = block_sum(L, above);  // its barrier also completes the histogram
+        // thread t owns buckets [t * per, min(nb, (t + 1) * per))
+        const int per = (nb + 255) / 256;
+        const int j0 = min(nb, tid * per), j1 = min(nb, j0 + per);
+        int cs = 0;
+        for (int j = j0; j < j1; ++j) cs += L->hist[j];
+        // inclusive suffix sums of the chunk sums (Hillis-Steele)
+        L->scan[tid] = cs;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int add = tid + o < 256 ? L->scan[tid + o] : 0;
+            __syncthreads();
+            L->scan[tid] += add;
+            __syncthreads();
+        }
+        int run = above + L->scan[tid] - cs;  // entries in later chunks or above hi
+        int best = -1;
+        for (int j = j1 - 1; j >= j0; --j) {
+            run += L->hist[j];
+            if (run >= lo + j * W) {
+                best = j;
+                break;
+            }
+        }
+        best = block_max(L, best);
+        lo += best * W;
+        if (W == 1) break;
+        hi = min(hi, lo + W - 1);
+    }
+    return lo;
+}
+
 // One vertex of degree >= kFeatHeavy per workgroup of 256 threads.
-// h-index by histogram refinement: it lies in [lo, hi] with f(lo) >= lo,
-// where f(k) = number of neighbours of degree >= k.  One pass over the row
-// histograms the (clamped) degrees in [lo, hi] into at most kHistBins buckets
-// of width W; the largest bucket start k with f(k) >= k narrows the range to
-// that bucket, and width 1 gives h exactly (at most three passes for any
-// 32-bit degree, one when the range is below kHistBins).
 __device__ void features_heavy(HeavyLds* L, int v, const int* __restrict__ row_ptr, const int* __restrict__ col,
                                uint64_t seed, float* __restrict__ out) {
     const int tid = threadIdx.x;
@@ -261,50 +319,8 @@ __device__ void features_heavy(HeavyLds* L, int v, const int* __restrict__ row_p
     sum = L->wl[0] + L->wl[1] + L->wl[2] + L->wl[3];
     __syncthreads();
 
-    const int cap = min(d, mx);
-    int lo = 0, hi = cap;
-    for (;;) {
-        const int span = hi - lo + 1;
-        const int W = (span + kHistBins - 1) / kHistBins;
-        const int nb = (span + W - 1) / W;
-        for (int j = tid; j < nb; j += 256) L->hist[j] = 0;
-        __syncthreads();
-        int above = 0;
-        for (int p = s + tid; p < e; p += 256) {
-            const int w = col[p];
-            const int c = min(row_ptr[w + 1] - row_ptr[w], cap);
-            if (c > hi) ++above;
-            else if (c >= lo) atomicAdd(&L->hist[(c - lo) / W], 1);
-        }
-        above = block_sum(L, above);  // its barrier also completes the histogram
-        // thread t owns buckets [t * per, min(nb, (t + 1) * per))
-        const int per = (nb + 255) / 256;
-        const int j0 = min(nb, tid * per), j1 = min(nb, j0 + per);
-        int cs = 0;
-        for (int j = j0; j < j1; ++j) cs += L->hist[j];
-        // inclusive suffix sums of the chunk sums (Hillis-Steele)
-        L->scan[tid] = cs;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const int add = tid + o < 256 ? L->scan[tid + o] : 0;
-            __syncthreads();
-            L->scan[tid] += add;
-            __syncthreads();
-        }
-        int run = above + L->scan[tid] - cs;  // neighbours in later chunks or above hi
-        int best = -1;
-        for (int j = j1 - 1; j >= j0; --j) {
-            run += L->hist[j];
-            if (run >= lo + j * W) {
-                best = j;
-                break;
-            }
-        }
-        best = block_max(L, best);
-        lo += best * W;
-        if (W == 1) break;
-        hi = min(hi, lo + W - 1);
-    }
+    const int lo = block_h_index(L, col, s, e, min(d, mx),
+                                 [row_ptr](int w) { return row_ptr[w + 1] - row_ptr[w]; });
     int closed = 0;
     if (tid < 64) {
         if (tid < kWedges) closed = wedge_closed(row_ptr, col, v, s, d, tid, seed);
@@ -324,6 +340,74 @@ __global__ __launch_bounds__(256) void k_features_heavy(const int* __restrict__ 
         features_heavy(&L, heavy[i], row_ptr, col, seed, out);
         __syncthreads();  // LDS reuse by the next vertex
     }
+}
+
+// ---------------------------------------------------------------------------
+// Core estimate: the H operator (h-index of the neighbours' values) applied
+// kCoreSteps times to the degrees (Lu et al., "The H-index of a network
+// node and its relation to degree and coreness", 2016: the sequence falls
+// monotonically to the coreness).  Step 1 is the h-index of the neighbour
+// degrees that the feature kernels compute; each further step reads the
+// previous step's values.  Light vertices (degree < kFeatHeavy) take 8
+// lanes with the values in registers; heavy ones reuse the feature kernels'
+// list and take a workgroup each with the same histogram refinement.
+// ---------------------------------------------------------------------------
+constexpr int kCoreSteps = 4;
+
+__global__ __launch_bounds__(256) void k_hstep(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                               const int* __restrict__ hin, int* __restrict__ hout) {
+    constexpr int GS = 8;
+    constexpr int kPer = kFeatHeavy / GS;
+    const int groups = gridDim.x * (256 / GS);
+    const int lig = threadIdx.x & (GS - 1);
+    for (int v = blockIdx.x * (256 / GS) + threadIdx.x / GS; v < n; v += groups) {
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        const int d = e - s;
+        if (d >= kFeatHeavy) continue;  // the heavy kernel's vertex (the whole group skips it)
+        int hv[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int q = s + lig + j * GS;
+            hv[j] = q < e ? col[q] : -1;
+        }
+        int mx = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            hv[j] = hv[j] >= 0 ? hin[hv[j]] : -1;
+            mx = max(mx, hv[j]);
+        }
+#pragma unroll
+        for (int o = GS / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, GS));
+        const int h = group_h_index<GS, kPer>(hv, min(d, mx));
+        if (lig == 0) hout[v] = h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hstep_heavy(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                     const int* __restrict__ heavy,
+                                                     const int* __restrict__ heavy_count,
+                                                     const int* __restrict__ hin, int* __restrict__ hout) {
+    __shared__ HeavyLds L;
+    const int total = *heavy_count;
+    for (int i = blockIdx.x; i < total; i += gridDim.x) {
+        const int v = heavy[i];
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        int mx = 0;
+        for (int q = s + threadIdx.x; q < e; q += 256) mx = max(mx, hin[col[q]]);
+        mx = block_max(&L, mx);
+        const int h = block_h_index(&L, col, s, e, min(e - s, mx), [hin](int w) { return hin[w]; });
+        if (threadIdx.x == 0) hout[v] = h;
+        __syncthreads();  // LDS reuse by the next vertex
+    }
+}
+
+// The first step's values from the feature array, the last step's into it.
+__global__ __launch_bounds__(256) void k_core_in(int n, const float* __restrict__ feat, int* __restrict__ h) {
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) h[v] = (int)feat[(size_t)v * kF + 7];
+}
+
+__global__ __launch_bounds__(256) void k_core_out(int n, const int* __restrict__ h, float* __restrict__ feat) {
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) feat[(size_t)v * kF + 7] = (float)h[v];
 }
 
 __global__ void k_zero_count(int* c) {
@@ -775,7 +859,8 @@ extern "C" {
 
 size_t gcolor_features_workspace_bytes(int32_t n) {
     if (n < 0) return 0;
-    return ((size_t)n + 64) * sizeof(int);
+    // heavy-vertex list (count + ids), then two arrays for the core-estimate steps
+    return ((size_t)n + 64) * sizeof(int) + (kCoreSteps > 1 ? 2 * (size_t)n * sizeof(int) : 0);
 }
 
 int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint64_t seed, float* feat_out,
@@ -791,6 +876,17 @@ int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, u
     k_features<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, seed, feat_out, list, count);
     // one workgroup per listed vertex (grid-strided over the device count)
     k_features_heavy<<<grid_for(n, kFeatHeavy), 256, 0, st>>>(row_ptr, col_idx, seed, list, count, feat_out);
+    if (kCoreSteps > 1) {
+        int* h0 = list + n;
+        int* h1 = h0 + n;
+        k_core_in<<<grid_for(n, 256), 256, 0, st>>>(n, feat_out, h0);
+        for (int step = 2; step <= kCoreSteps; ++step) {
+            k_hstep<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, h0, h1);
+            k_hstep_heavy<<<grid_for(n, kFeatHeavy), 256, 0, st>>>(row_ptr, col_idx, list, count, h0, h1);
+            std::swap(h0, h1);
+        }
+        k_core_out<<<grid_for(n, 256), 256, 0, st>>>(n, h0, feat_out);
+    }
     return hipGetLastError() == hipSuccess ? GCOLOR_OK : GCOLOR_EHIP;
 }
 

@@ -54,11 +54,14 @@ def test_features_against_loops():
     deg = [len(a) for a in adj]
     F = OL.features(g.row_ptr, g.col_idx, seed=11)
     eset = {(u, w) for u in range(g.n) for w in adj[u]}
+    x = list(deg)
+    for _ in range(OL.CORE_STEPS):
+        x = [max([k for k in range(deg[v] + 1) if sum(1 for w in adj[v] if x[w] >= k) >= k], default=0)
+             for v in range(g.n)]
     for v in range(g.n):
         nd = [deg[w] for w in adj[v]]
         d = deg[v]
-        h = max([k for k in range(d + 1) if sum(1 for x in nd if x >= k) >= k], default=0)
-        assert F[v, 7] == h
+        assert F[v, 7] == x[v]
         if d:
             assert F[v, 2] == min(nd) and F[v, 4] == max(nd) and np.isclose(F[v, 3], sum(nd) / d)
             assert F[v, 5] == sum(x - 1 for x in nd)
@@ -71,6 +74,77 @@ def test_features_against_loops():
                 b += b >= a
                 closed += (adj[v][a], adj[v][b]) in eset
             assert np.isclose(F[v, 6], closed / 8 * d * (d - 1) / 2)
+
+
+def _coreness_by_peeling(adj):
+    """Core numbers from their definition: repeatedly delete a vertex of
+    least remaining degree; a vertex's core number is the largest such
+    least degree seen up to its deletion."""
+    n = len(adj)
+    alive = set(range(n))
+    deg = {v: len(set(adj[v]) - {v}) for v in range(n)}
+    core = [0] * n
+    k = 0
+    while alive:
+        v = min(alive, key=lambda u: (deg[u], u))
+        k = max(k, deg[v])
+        core[v] = k
+        alive.remove(v)
+        for w in set(adj[v]) - {v}:
+            if w in alive:
+                deg[w] -= 1
+    return core
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 9, 16])
+def test_core_estimate_on_paths(n):
+    """Path 0 - 1 - ... - (n-1): after k steps a vertex at distance j from the
+    nearer end holds 1 if j <= k, else 2 (step 0 is the degrees; each step
+    carries the ends' 1 one vertex inward, since an interior vertex keeps 2
+    only while both neighbours hold 2)."""
+    g = graphgen.path(n)
+    for k in range(n + 1):
+        h = OL.core_estimate(g.row_ptr, g.col_idx, k)
+        want = [1 if min(v, n - 1 - v) <= k else 2 for v in range(n)]
+        assert list(h) == want, (n, k)
+
+
+def test_core_estimate_falls_to_the_coreness():
+    """The H sequence never rises, stays at or above the core numbers at
+    every step, and reaches them (Lu et al. 2016); n steps always suffice on
+    these graphs.  Core numbers come from peeling, not from H."""
+    rng = np.random.default_rng(3)
+    graphs = [graphgen.rmat(9, 8, (0.57, 0.19, 0.19), 1), graphgen.star(12, 4), graphgen.complete(6),
+              graphgen.grid((5, 7), True)]
+    for _ in range(60):
+        n = int(rng.integers(2, 24))
+        p = rng.uniform(0.05, 0.6)
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+        rp, ci = oracle.adj_to_csr(oracle.edges_to_adj(n, edges))
+        graphs.append((n, rp, ci))
+    for g in graphs:
+        n, rp, ci = (g.n, g.row_ptr, g.col_idx) if isinstance(g, graphgen.CSR) else g
+        core = np.array(_coreness_by_peeling(oracle.adjacency(rp, ci)))
+        prev = np.diff(np.asarray(rp, dtype=np.int64))
+        for k in range(1, n + 2):
+            h = OL.core_estimate(rp, ci, k)
+            assert np.all(h <= prev) and np.all(h >= core), k
+            prev = h
+        assert np.array_equal(prev, core)
+
+
+def test_core_estimate_on_a_clique_with_a_tail():
+    """K_5 on vertices 0..4 with a path 4 - 5 - 6 - 7 hanging off vertex 4:
+    the clique's core number is 4 and the tail's 1; the clique vertices hold
+    4 from the first step on (four neighbours of degree >= 4), the tail's
+    end 7 holds 1 from the start, vertex 6 drops to 1 at the first step (its
+    neighbour 7 has degree 1) and vertex 5 at the second (its neighbour 6
+    then holds 1)."""
+    edges = [(i, j) for i in range(5) for j in range(i + 1, 5)] + [(4, 5), (5, 6), (6, 7)]
+    rp, ci = oracle.adj_to_csr(oracle.edges_to_adj(8, edges))
+    assert list(OL.core_estimate(rp, ci, 0)) == [4, 4, 4, 4, 5, 2, 2, 1]
+    assert list(OL.core_estimate(rp, ci, 1)) == [4, 4, 4, 4, 4, 2, 1, 1]
+    assert list(OL.core_estimate(rp, ci, 2)) == [4, 4, 4, 4, 4, 1, 1, 1]
 
 
 def _random_model(seed):
