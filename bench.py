@@ -778,6 +778,10 @@ def bench_learned(args):
     rank, degen = L.smallest_last_rank(ev.row_ptr, ev.col_idx)
     t_sl_order = (time.perf_counter() - w) * 1000.0
     slk = torch.from_numpy(rank.astype(np.int32)).to(dev)
+    # the same order on the device (one workgroup walks the removals)
+    t_sl_gpu, (gpu_rank, gpu_degen) = timed(lambda: gc.smallest_last(rp, ci), 1)
+    sl_gpu_equal = bool(torch.equal(gpu_rank, slk)) and gpu_degen == degen
+    log("device smallest-last %.1f ms, equal to the host order: %s" % (t_sl_gpu, sl_gpu_equal))
     t_sl_col, c_sl = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, stats=True)[1].num_colors, reps)
     t_sl_flow, st_sl_flow = timed(lambda: gc.color_graph_ex(rp, ci, slk, out, flags=gc.FLAG_DATAFLOW,
                                                             stats=True)[1], reps)
@@ -806,8 +810,11 @@ def bench_learned(args):
                "learned_dataflow": round(t_lflow, 3),
                "exact_smallest_last_order_host": round(t_sl_order, 1),
                "exact_smallest_last_total": round(t_sl_order + t_sl_col, 1),
+               "exact_smallest_last_order_gpu": round(t_sl_gpu, 1),
+               "exact_smallest_last_total_gpu": round(t_sl_gpu + t_sl_col, 1),
                "exact_smallest_last_dataflow_colouring": round(t_sl_flow, 3)},
         "dataflow_rounds": {"learned": int(st_lflow.rounds), "exact_smallest_last": int(st_sl_flow.rounds)},
+        "smallest_last_gpu_equals_host": sl_gpu_equal,
         "training": {"seconds": round(train_s, 2), "vertices": rep.vertices, "final_minibatch_loss":
                      round(rep.losses[-1], 6)},
     }

@@ -190,7 +190,7 @@ int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
  * first call there); the caller still passes inputs and outputs as for
  * color_graph_async.  Graphs whose gcolor_workspace_bytes(n, nnz) exceeds the
  * array are refused with GCOLOR_ENOTSUP before any device work (about
- * 230,000 vertices at 10 entries per vertex).  Every call on a device shares
+ * 358,000 vertices at 10 entries per vertex).  Every call on a device shares
  * that device's array, which keeps the last call's contents: calls that
  * overlap on one device (other streams or threads) race and must be
  * serialised by the caller.  Other errors and stats_dev: as
@@ -437,6 +437,28 @@ int gcolor_order_learned(int32_t n, const int32_t* row_ptr, const int32_t* col_i
  * takes a minimum-degree vertex, the smallest id among them). */
 int gcolor_smallest_last_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* rank,
                               int32_t* degeneracy);
+
+/* Exact smallest-last order on the device (Matula and Beck 1983; the paper's
+ * section "Number of colors" cites it among the orderings that bound the
+ * colours of the greedy scheme).  The same order as
+ * gcolor_smallest_last_host: each removal takes a vertex of least remaining
+ * degree, the smallest id among them; rank[v] (device, int32[n], written) is
+ * v's position in the colouring order, n - 1 minus its removal step, so
+ * rank works directly as a colour_graph priority.  row_ptr / col_idx: device
+ * CSR, symmetric, no duplicate entries (self-loops are ignored); col_idx may
+ * be NULL when no row has entries.
+ * *degeneracy (host, may be NULL) receives the largest least degree met.
+ * One workgroup walks the removals, many per step: the longest run of the
+ * smallest ids of the least degree that the one-at-a-time process removes in
+ * id order.  Synchronous on `stream`: allocates its own device memory (degree
+ * buckets as bitmaps: about n/8 bytes per degree up to a bound of the
+ * degeneracy) and returns when the ranks are written.
+ * Errors: GCOLOR_EINVAL (n < 0, NULL row_ptr or rank), GCOLOR_ECSR
+ * (decreasing row offsets, an entry outside [0, n), or entries with a NULL
+ * col_idx), GCOLOR_ENOTSUP (n > 2^28),
+ * GCOLOR_EHIP, GCOLOR_EINTERNAL. */
+int gcolor_smallest_last(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* rank,
+                         int32_t* degeneracy, gcolor_stream_t stream);
 
 /* Human-readable name of a return code. */
 const char* gcolor_strerror(int code);

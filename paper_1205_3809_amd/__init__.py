@@ -42,6 +42,7 @@ from ._binding import (  # noqa: F401
     profile_read,
     raw_library,
     set_tuning,
+    smallest_last,
     batch_workspace_bytes,
     color_graph_batch,
     wall_clock_khz,

@@ -129,9 +129,11 @@ def _load():
     lib.gcolor_mlp_refresh_bf16.argtypes = [vp, vp, vp]
     lib.gcolor_scores_to_keys.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
     lib.gcolor_smallest_last_host.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
+    lib.gcolor_smallest_last.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
     for f in ("gcolor_features", "gcolor_feature_stats", "gcolor_feature_norm", "gcolor_rank_targets",
               "gcolor_order_learned", "gcolor_mlp_forward", "gcolor_mlp_grad", "gcolor_mlp_adam",
-              "gcolor_mlp_refresh_bf16", "gcolor_scores_to_keys", "gcolor_smallest_last_host"):
+              "gcolor_mlp_refresh_bf16", "gcolor_scores_to_keys", "gcolor_smallest_last_host",
+              "gcolor_smallest_last"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -311,6 +313,24 @@ def color_graph(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     if rc != 0:
         raise GColorError(rc, "color_graph")
     return colors_out
+
+
+def smallest_last(row_ptr: torch.Tensor, col_idx: torch.Tensor, rank_out: Optional[torch.Tensor] = None,
+                  stream=None):
+    """Exact smallest-last order on the device: returns (rank, degeneracy),
+    rank[v] = v's position in the colouring order (int32, on the device)."""
+    n = row_ptr.numel() - 1
+    rp = _dev_ptr(row_ptr, "row_ptr", _I32)
+    ci = _dev_ptr(col_idx, "col_idx", _I32)
+    if rank_out is None:
+        rank_out = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    ro = _dev_ptr(rank_out, "rank_out", _I32, n)
+    deg = ctypes.c_int32()
+    with torch.cuda.device(row_ptr.device):
+        rc = _lib.gcolor_smallest_last(n, rp, ci, ro, ctypes.byref(deg), _stream_handle(stream))
+    if rc != 0:
+        raise GColorError(rc, "gcolor_smallest_last")
+    return rank_out, int(deg.value)
 
 
 def set_tuning(bin_limits=None, blocks_per_cu: int = 0) -> None:

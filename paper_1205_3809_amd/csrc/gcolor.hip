@@ -108,7 +108,8 @@ struct Ctl {
     int32_t maxdeg;
     unsigned long long committed;  // vertices committed so far
     int32_t nheavy;                // (incremental) rows with an active copy
-    int32_t pad[9];
+    int32_t binpop[kBins];         // vertices whose degree falls in each bin
+    int32_t pad[4];
 };
 static_assert(sizeof(Ctl) == 320, "ctl layout");
 
@@ -122,7 +123,7 @@ struct Args {
     void* st;                      // (incremental) state words, int8_t, int16_t or int32_t
     int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
-    int* __restrict__ lists;       // [kSets][kBins][n]
+    int* __restrict__ lists;       // [kSets][n], bins at the offsets of their populations
     unsigned* __restrict__ dbits;  // (incremental) 3 dirty bitmaps of nwords words
     unsigned* __restrict__ bplane; // (incremental) each vertex's degree bin as 3 bit planes of nwords words
     int nwords;
@@ -154,8 +155,18 @@ __device__ __forceinline__ int bin_of(int deg, const BinCfg& c) {
     return deg <= c.dmax[0] ? 0 : deg <= c.dmax[1] ? 1 : deg <= c.dmax[2] ? 2 : deg <= c.dmax[3] ? 3 : 4;
 }
 
+// Each list set is one n-entry array: bin b starts after the populations of
+// bins 0..b-1 (a vertex only ever enters the bin of its degree, and no set
+// holds a vertex twice, so a bin never outgrows its population).
+__device__ __forceinline__ int bin_offset(const Ctl* ctl, int b) {
+    int off = 0;
+#pragma unroll
+    for (int i = 0; i < kBins - 1; ++i) off += i < b ? ctl->binpop[i] : 0;
+    return off;
+}
+
 __device__ __forceinline__ int* list_ptr(const Args& a, int set, int b) {
-    return a.lists + ((size_t)(set * kBins + b)) * (size_t)a.n;
+    return a.lists + (size_t)set * (size_t)a.n + bin_offset(a.ctl, b);
 }
 
 template <int GS>
@@ -334,6 +345,7 @@ __device__ __forceinline__ void stage_maybe_flush(const Args& a, Stage* st, int 
 struct ChunkMap {
     int cnt[kBins];
     int start[kBins];  // chunk-space start of each bin; bins ordered 4,3,2,1,0
+    int off[kBins];    // bin offsets inside the set's array
     int total;
 };
 
@@ -344,6 +356,11 @@ __device__ __forceinline__ ChunkMap make_map(const Ctl* ctl, int set) {
         m.cnt[b] = ctl->cnt[set][b];
         m.start[b] = tot;
         tot += (m.cnt[b] + chunk_vertices(b) - 1) / chunk_vertices(b);
+    }
+    int off = 0;
+    for (int b = 0; b < kBins; ++b) {
+        m.off[b] = off;
+        off += ctl->binpop[b];
     }
     m.total = tot;
     return m;
@@ -417,7 +434,7 @@ __device__ __forceinline__ int first_fit_block(int s, int e, int base, const int
         for (int c_ = blockIdx.x; c_ < m_.total; c_ += gridDim.x) {                     \
             const int b_ = chunk_bin(m_, c_);                                          \
             const int local_ = c_ - pick5(m_.start, b_);                                      \
-            const int* list_ = list_ptr((A), (SET), b_);                               \
+            const int* list_ = (A).lists + (size_t)(SET) * (size_t)(A).n + pick5(m_.off, b_); \
             const int cnt_ = pick5(m_.cnt, b_);                                               \
             switch (b_) {                                                              \
                 case 0: BODY_GS(1, list_, cnt_, local_); break;                        \
@@ -436,7 +453,7 @@ __device__ __forceinline__ int first_fit_block(int s, int e, int base, const int
         for (int c_ = blockIdx.x; c_ < (M).total; c_ += gridDim.x) {                    \
             const int b_ = chunk_bin((M), c_);                                         \
             const int local_ = c_ - pick5((M).start, b_);                                     \
-            const int* list_ = list_ptr((A), (SET), b_);                               \
+            const int* list_ = (A).lists + (size_t)(SET) * (size_t)(A).n + pick5((M).off, b_); \
             const int cnt_ = pick5((M).cnt, b_);                                              \
             switch (b_) {                                                              \
                 case 0: BODY_GS(1, list_, cnt_, local_); break;                        \
@@ -1288,6 +1305,7 @@ __host__ __device__ constexpr int wchunk(int b) { return b == 0 ? 64 : b == 1 ? 
 struct WaveMap {
     int cnt[4];
     int start[4];
+    int off[4];  // bin offsets inside the set's array
     int total;
 };
 
@@ -1298,6 +1316,11 @@ __device__ __forceinline__ WaveMap make_wave_map(const Ctl* ctl, int set) {
         m.cnt[b] = ctl->cnt[set][b];
         m.start[b] = tot;
         tot += (m.cnt[b] + wchunk(b) - 1) / wchunk(b);
+    }
+    int off = 0;
+    for (int b = 0; b < 4; ++b) {
+        m.off[b] = off;
+        off += ctl->binpop[b];
     }
     m.total = tot;
     return m;
@@ -1318,7 +1341,7 @@ __device__ __forceinline__ int wave_chunk_entry(const Args& a, const WaveMap& m,
     if (c >= m.total) return INT_MIN;
     const int b = wave_chunk_bin(m, c);
     const int idx = (c - pick4(m.start, b)) * wchunk(b) + lane / (kWave / wchunk(b));
-    return idx < pick4(m.cnt, b) ? list_ptr(a, set, b)[idx] : INT_MIN;
+    return idx < pick4(m.cnt, b) ? a.lists[(size_t)set * (size_t)a.n + pick4(m.off, b) + idx] : INT_MIN;
 }
 
 // Round k, kernel A.  Also clears the bitmap of round k-1's dirty vertices
@@ -2058,6 +2081,27 @@ __global__ __launch_bounds__(kBlock) void k_setup_natural(Args a, int* split) {
 }
 
 // Priority order, step 1: clear colours and bin every vertex.
+// Vertices per degree bin (the list sets place bin b after bins 0..b-1).
+__global__ __launch_bounds__(kBlock) void k_bin_pop(Args a) {
+    __shared__ int h[kBins];
+    if (a.ctl->err) return;  // the CSR failed validation: nothing is read
+    if (threadIdx.x < kBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    int c[kBins] = {0, 0, 0, 0, 0};
+    for (int v = blockIdx.x * kBlock + (int)threadIdx.x; v < a.n; v += gridDim.x * kBlock) {
+        const int b = bin_of(a.row_ptr[v + 1] - a.row_ptr[v], a.cfg);
+#pragma unroll
+        for (int i = 0; i < kBins; ++i) c[i] += b == i;
+    }
+#pragma unroll
+    for (int i = 0; i < kBins; ++i) {
+        const int x = group_sum<kWave>(c[i]);
+        if (__lane_id() == 0 && x) atomicAdd(&h[i], x);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins && h[threadIdx.x]) atomicAdd(&a.ctl->binpop[threadIdx.x], h[threadIdx.x]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_setup_bins(Args a) {
     __shared__ Stage st;
     if (a.ctl->err) return;  // the CSR failed validation: nothing is read
@@ -2287,7 +2331,7 @@ Layout layout(int32_t n, int64_t nnz) {
     L.conf = off;  off += align_up(vn);
     L.cflag = off; off += align_up(vn);
     L.split = off; off += align_up(vn);
-    L.lists = off; off += align_up(vn * kSets * kBins);
+    L.lists = off; off += align_up(vn * kSets);
     L.dbits = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.bplane = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.bcnt = off;  off += align_up(sizeof(int32_t) * 8 * (size_t)kCompactMaxBlocks);
@@ -2817,6 +2861,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     }
 
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         // rows reordered so that the neighbours preceding v come first
         int* colp = reinterpret_cast<int*>(base + Lw.colp);
@@ -2950,6 +2995,7 @@ int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
     Args a = make_args(n, nnz, row_ptr, col_idx, colors, base, Lw, ctl, log);
     const bool natural = priority == nullptr;
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         int* colp = reinterpret_cast<int*>(base + Lw.colp);
         k_setup_bins<<<vgrid, kBlock, 0, st>>>(a);

@@ -69,7 +69,8 @@ def test_workspace_bytes_grows_with_size():
     b = gc.workspace_bytes(2000, 5000)
     c = gc.workspace_bytes(2000, 50000)
     assert 0 < a < b < c
-    # per vertex: tent, split and 10 worklist slots; per entry: the reordered row
+    # per vertex: five state arrays, six list slots and the heavy-row id; per
+    # entry: the reordered row
     assert b - a >= 48 * 1000 - 2048 and c - b >= 4 * 45000 - 256
     assert gc.workspace_bytes(-1, 0) == 0
 
@@ -104,6 +105,13 @@ def test_argument_errors_before_any_device_work():
     assert lib.gcolor_order_learned(5, fake, fake, 1, fake, fake, fake, fake, None, fake, 1 << 20, None) == -1
     assert lib.gcolor_feature_norm(0, fake, fake, None) == -1
     assert lib.gcolor_rank_targets(-1, fake, fake, None) == -1
+    # device smallest-last: negative n, empty graph, NULL arrays, n beyond 2^28
+    deg = ctypes.c_int32(-5)
+    assert lib.gcolor_smallest_last(-1, fake, fake, fake, None, None) == -1
+    assert lib.gcolor_smallest_last(0, None, None, None, ctypes.byref(deg), None) == 0 and deg.value == 0
+    assert lib.gcolor_smallest_last(5, None, fake, fake, None, None) == -1
+    assert lib.gcolor_smallest_last(5, fake, fake, None, None, None) == -1
+    assert lib.gcolor_smallest_last((1 << 28) + 1, fake, fake, fake, None, None) == -6
 
 
 def test_tuning_validation():
