@@ -388,22 +388,37 @@ __global__ __launch_bounds__(256) void k_hstep_heavy(const int* __restrict__ row
                                                      const int* __restrict__ heavy_count,
                                                      const int* __restrict__ hin, int* __restrict__ hout) {
     __shared__ HeavyLds L;
-    const int total = *heavy_count;
+    const int total = heavy_count[0];
+    // every value is at most the largest first-step value (the H sequence
+    // never rises), so that bounds the search with no pass for the row's
+    // largest value: one histogram pass of width 1 while it is below
+    // kHistBins
+    const int bound = heavy_count[1];
     for (int i = blockIdx.x; i < total; i += gridDim.x) {
         const int v = heavy[i];
         const int s = row_ptr[v], e = row_ptr[v + 1];
-        int mx = 0;
-        for (int q = s + threadIdx.x; q < e; q += 256) mx = max(mx, hin[col[q]]);
-        mx = block_max(&L, mx);
-        const int h = block_h_index(&L, col, s, e, min(e - s, mx), [hin](int w) { return hin[w]; });
+        const int h = block_h_index(&L, col, s, e, min(e - s, bound), [hin](int w) { return hin[w]; });
         if (threadIdx.x == 0) hout[v] = h;
         __syncthreads();  // LDS reuse by the next vertex
     }
 }
 
-// The first step's values from the feature array, the last step's into it.
-__global__ __launch_bounds__(256) void k_core_in(int n, const float* __restrict__ feat, int* __restrict__ h) {
-    for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) h[v] = (int)feat[(size_t)v * kF + 7];
+// The first step's values from the feature array (and their largest value
+// into *hmax), the last step's into it.
+__global__ __launch_bounds__(256) void k_core_in(int n, const float* __restrict__ feat, int* __restrict__ h,
+                                                 int* __restrict__ hmax) {
+    __shared__ int wm[4];
+    int mx = 0;
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+        const int x = (int)feat[(size_t)v * kF + 7];
+        h[v] = x;
+        mx = max(mx, x);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(hmax, max(max(wm[0], wm[1]), max(wm[2], wm[3])));
 }
 
 __global__ __launch_bounds__(256) void k_core_out(int n, const int* __restrict__ h, float* __restrict__ feat) {
@@ -411,7 +426,7 @@ __global__ __launch_bounds__(256) void k_core_out(int n, const int* __restrict__
 }
 
 __global__ void k_zero_count(int* c) {
-    if (threadIdx.x == 0) c[0] = 0;
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;  // heavy-list length, largest first-step core estimate
 }
 
 // Per-feature sum and sum of squares of log1p(feature), in double.
@@ -879,7 +894,7 @@ int gcolor_features(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, u
     if (kCoreSteps > 1) {
         int* h0 = list + n;
         int* h1 = h0 + n;
-        k_core_in<<<grid_for(n, 256), 256, 0, st>>>(n, feat_out, h0);
+        k_core_in<<<grid_for(n, 256), 256, 0, st>>>(n, feat_out, h0, count + 1);
         for (int step = 2; step <= kCoreSteps; ++step) {
             k_hstep<<<grid_for(n, 32), 256, 0, st>>>(n, row_ptr, col_idx, h0, h1);
             k_hstep_heavy<<<grid_for(n, kFeatHeavy), 256, 0, st>>>(row_ptr, col_idx, list, count, h0, h1);
