@@ -130,17 +130,32 @@ __device__ int wg_scan(int x, int* ws, int& total) {
 // Degrees without self-loops, ranks unset, and the histogram of degrees
 // (capped at kDegCap) that bounds the degeneracy; *bad is set when a row's
 // offsets decrease, an entry lies outside [0, n), or col is NULL under a
-// non-empty row.
+// non-empty row.  Rows longer than kLongRow are listed for k_peel_long
+// (a workgroup each) instead of one thread walking them.
+constexpr int kLongRow = 64;
+
+__device__ __forceinline__ void hist_add(int* h, int* hist, int d) {
+    if (d < kLdsHist) atomicAdd(&h[d], 1);
+    else atomicAdd(&hist[min(d, kDegCap)], 1);
+}
+
 __global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
                                                    int* __restrict__ deg, int* __restrict__ rank,
-                                                   int* __restrict__ hist, int* __restrict__ bad) {
+                                                   int* __restrict__ hist, int* __restrict__ bad,
+                                                   int* __restrict__ longs, int* __restrict__ nlong) {
     __shared__ int h[kLdsHist];
     for (int i = threadIdx.x; i < kLdsHist; i += 256) h[i] = 0;
     __syncthreads();
     for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
         const int s = row_ptr[v], e = row_ptr[v + 1];
+        rank[v] = -1;
         if (e < s || (v == 0 && s != 0) || (e > s && col == nullptr)) {
             atomicOr(bad, 1);
+            deg[v] = 0;
+            continue;
+        }
+        if (e - s > kLongRow) {
+            longs[atomicAdd(nlong, 1)] = v;
             continue;
         }
         int d = 0;
@@ -150,13 +165,39 @@ __global__ __launch_bounds__(256) void k_peel_init(int n, const int* __restrict_
             d += w != v;
         }
         deg[v] = d;
-        rank[v] = -1;
-        if (d < kLdsHist) atomicAdd(&h[d], 1);
-        else atomicAdd(&hist[min(d, kDegCap)], 1);
+        hist_add(h, hist, d);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kLdsHist; i += 256)
         if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ __launch_bounds__(256) void k_peel_long(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                                   int* __restrict__ deg, int* __restrict__ hist,
+                                                   int* __restrict__ bad, const int* __restrict__ longs,
+                                                   const int* __restrict__ nlong) {
+    __shared__ int part[4];
+    const int total = *nlong;
+    for (int i = blockIdx.x; i < total; i += gridDim.x) {
+        const int v = longs[i];
+        const int s = row_ptr[v], e = row_ptr[v + 1];
+        int loops = 0;
+        for (int p = s + (int)threadIdx.x; p < e; p += 256) {
+            const int w = col[p];
+            if (w < 0 || w >= n) atomicOr(bad, 1);
+            loops += w == v;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) loops += __shfl_xor(loops, o);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = loops;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int d = (e - s) - (part[0] + part[1] + part[2] + part[3]);
+            deg[v] = d;
+            atomicAdd(&hist[min(d, kDegCap)], 1);
+        }
+        __syncthreads();  // part is reused by the next row
+    }
 }
 
 // Every vertex into the bucket of its degree (degrees above the bound stay
@@ -185,20 +226,36 @@ struct PeelLds {
     int pd[kPairs];        // its degree at the start of the step
     short pq[kPairs];      // the pair's candidate position
     short pp[kPairs];      // the neighbour's own candidate position, -1 if none
-    int pnext[kPairs];     // next pair with the same neighbour
-    int pslot[kPairs];     // hash slot of the neighbour (-1: pair not used)
+    short pnext[kPairs];   // next pair with the same neighbour
+    short pslot[kPairs];   // hash slot of the neighbour (-1: pair not used)
     int hkey[kHash];
     int hhead[kHash];
     int hcount[kHash];
     int hmin[kHash];
     int htk[kHash];        // hits by the removed candidates
     int cnt[kCntLds];      // bucket counts (when the bound is below kCntLds)
+    int nxt[kChunk];       // the next step's candidates, when known without a scan
+    int lj[kChunk];        // neighbours left at delta - 1 (from the front) or delta (from the back)
     int l1idx[16];
     u64 l1w[16];
     int ws[kT / 64];
     int found, np, cut, istar;
     int removed, delta, chunk, degen, err;
+    int nlow, njoin, njp, nnext, ndelta;
 };
+
+// A neighbour whose new degree is delta - 1 or delta may be a candidate of
+// the next step: listed from the front and the back of lj (an overflow is
+// seen from the two counts).
+__device__ __forceinline__ void note_level(PeelLds& L, int y, int d1, int delta) {
+    if (d1 == delta - 1) {
+        const int k = atomicAdd(&L.nlow, 1);
+        if (k < kChunk) L.lj[k] = y;
+    } else if (d1 == delta) {
+        const int k = atomicAdd(&L.njoin, 1);
+        if (k < kChunk) L.lj[kChunk - 1 - k] = y;
+    }
+}
 
 __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
                                              int* deg, int* rank, Buckets b, PeelCtl* ctl) {
@@ -214,6 +271,7 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
         else atomicAdd(&b.cnt[d], x);
     };
     if (tid == 0) {
+        L.nnext = 0;
         L.removed = 0;
         L.delta = 0;
         L.chunk = 64;
@@ -229,78 +287,86 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
             if (tid == 0) L.err = 2;
             break;
         }
-        // least non-empty degree, from one below the last one up
-        if (tid == 0) L.found = INT_MAX;
-        __syncthreads();
-        for (int base = max(L.delta - 1, 0); base <= b.dcap; base += kT) {
-            const int d = base + tid;
-            if (d <= b.dcap && cnt_get(d) > 0) atomicMin(&L.found, d);
-            __syncthreads();
-            const int f = L.found;
-            __syncthreads();
-            if (f != INT_MAX) break;
-        }
-        const int delta = L.found;
-        if (delta == INT_MAX) {
-            if (tid == 0) L.err = 1;
-            break;
-        }
-        u64* B0 = b.l0(delta);
-        u64* B1 = B0 + b.w0;
-        u64* B2 = B1 + b.w1;
         const int K = L.chunk;
-
-        // the K smallest ids of degree delta (a pass that meets only stale
-        // upper-level bits clears them and looks again)
-        int m = 0;
-        bool bad = false;
-        for (long long pass = 0;; ++pass) {
-            const u64 w2 = tid < b.w2 ? ald64(&B2[tid]) : 0ull;
-            int tot2;
-            const int o2 = wg_scan(__popcll(w2), L.ws, tot2);
-            u64 x = w2;
-            for (int k = o2; x && k < 16; ++k) {
-                L.l1idx[k] = tid * 64 + __builtin_ctzll(x);
-                x &= x - 1;
-            }
+        const int carried = L.nnext;
+        int delta, m;
+        if (carried > 0) {
+            // candidates carried over from the previous step
+            delta = L.ndelta;
+            m = min(carried, K);
+            if (tid < m) L.cand[tid] = L.nxt[tid];
+        } else {
+            // least non-empty degree, from one below the last one up
+            if (tid == 0) L.found = INT_MAX;
             __syncthreads();
-            const int nl1 = min(tot2, 16);
-            if (nl1 == 0 || pass > b.w1 + b.w2 + 2) {
-                bad = true;
+            for (int base = max(L.delta - 1, 0); base <= b.dcap; base += kT) {
+                const int d = base + tid;
+                if (d <= b.dcap && cnt_get(d) > 0) atomicMin(&L.found, d);
+                __syncthreads();
+                const int f = L.found;
+                __syncthreads();
+                if (f != INT_MAX) break;
+            }
+            delta = L.found;
+            if (delta == INT_MAX) {
+                if (tid == 0) L.err = 1;
                 break;
             }
-            if (tid < nl1) {
-                const int i1 = L.l1idx[tid];
-                const u64 w1 = ald64(&B1[i1]);
-                L.l1w[tid] = w1;
-                if (w1 == 0ull) atomicAnd(&B2[i1 >> 6], ~(1ull << (i1 & 63)));
-            }
-            __syncthreads();
-            // thread t: level-1 word t / 64, bit t % 64 (ascending word order)
-            const int j = tid >> 6, bit = tid & 63;
-            u64 w0 = 0;
-            long long i0 = 0;
-            if (j < nl1 && (L.l1w[j] >> bit & 1ull)) {
-                i0 = (long long)L.l1idx[j] * 64 + bit;
-                w0 = ald64(&B0[i0]);
-                if (w0 == 0ull) atomicAnd(&B1[L.l1idx[j]], ~(1ull << bit));
-            }
-            int tot0;
-            const int o0 = wg_scan(__popcll(w0), L.ws, tot0);
-            x = w0;
-            for (int k = o0; x && k < K; ++k) {
-                L.cand[k] = (int)(i0 * 64 + __builtin_ctzll(x));
-                x &= x - 1;
-            }
-            __syncthreads();
-            m = min(tot0, K);
-            if (m > 0) break;
-        }
-        if (bad) {
-            if (tid == 0) L.err = 3;
-            break;
-        }
+            u64* B0 = b.l0(delta);
+            u64* B1 = B0 + b.w0;
+            u64* B2 = B1 + b.w1;
 
+            // the K smallest ids of degree delta (a pass that meets only stale
+            // upper-level bits clears them and looks again)
+            m = 0;
+            bool bad = false;
+            for (long long pass = 0;; ++pass) {
+                const u64 w2 = tid < b.w2 ? ald64(&B2[tid]) : 0ull;
+                int tot2;
+                const int o2 = wg_scan(__popcll(w2), L.ws, tot2);
+                u64 x = w2;
+                for (int k = o2; x && k < 16; ++k) {
+                    L.l1idx[k] = tid * 64 + __builtin_ctzll(x);
+                    x &= x - 1;
+                }
+                __syncthreads();
+                const int nl1 = min(tot2, 16);
+                if (nl1 == 0 || pass > b.w1 + b.w2 + 2) {
+                    bad = true;
+                    break;
+                }
+                if (tid < nl1) {
+                    const int i1 = L.l1idx[tid];
+                    const u64 w1 = ald64(&B1[i1]);
+                    L.l1w[tid] = w1;
+                    if (w1 == 0ull) atomicAnd(&B2[i1 >> 6], ~(1ull << (i1 & 63)));
+                }
+                __syncthreads();
+                // thread t: level-1 word t / 64, bit t % 64 (ascending word order)
+                const int j = tid >> 6, bit = tid & 63;
+                u64 w0 = 0;
+                long long i0 = 0;
+                if (j < nl1 && (L.l1w[j] >> bit & 1ull)) {
+                    i0 = (long long)L.l1idx[j] * 64 + bit;
+                    w0 = ald64(&B0[i0]);
+                    if (w0 == 0ull) atomicAnd(&B1[L.l1idx[j]], ~(1ull << bit));
+                }
+                int tot0;
+                const int o0 = wg_scan(__popcll(w0), L.ws, tot0);
+                x = w0;
+                for (int k = o0; x && k < K; ++k) {
+                    L.cand[k] = (int)(i0 * 64 + __builtin_ctzll(x));
+                    x &= x - 1;
+                }
+                __syncthreads();
+                m = min(tot0, K);
+                if (m > 0) break;
+            }
+            if (bad) {
+                if (tid == 0) L.err = 3;
+                break;
+            }
+        }
         // rows of the candidates
         int rlen = 0;
         if (tid < m) {
@@ -317,6 +383,9 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
             L.np = 0;
             L.cut = m;
             L.istar = INT_MAX;
+            L.nlow = 0;
+            L.njoin = 0;
+            L.njp = 0;
         }
         __syncthreads();
         // candidates whose rows end past the scan budget wait for a later step
@@ -455,6 +524,7 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
                 if (h < 0 || q != L.hmin[h] || q >= take || (pos >= 0 && pos < take)) continue;
                 const int y = L.py[i], d0 = L.pd[i], d1 = d0 - L.htk[h];
                 ast(&deg[y], d1);
+                note_level(L, y, d1, delta);
                 if (d0 <= b.dcap) {
                     b.clear(d0, y);
                     cnt_add(d0, -1);
@@ -474,6 +544,7 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
                 if (d0 < 0) continue;
                 const int d1 = d0 - 1;
                 ast(&deg[y], d1);
+                note_level(L, y, d1, delta);
                 if (d0 <= b.dcap) {
                     b.clear(d0, y);
                     cnt_add(d0, -1);
@@ -482,6 +553,61 @@ __global__ __launch_bounds__(kT) void k_peel(int n, const int* __restrict__ row_
                     b.set_all(d1, y);
                     cnt_add(d1, 1);
                 }
+            }
+        }
+        __syncthreads();
+        // the next step's candidates when they are known here: every vertex
+        // left at delta - 1 (none was below delta, so these are all of that
+        // degree); otherwise, with no candidate hit, the candidates not taken
+        // and the vertices that came down to delta, either all of degree
+        // delta or those below the last candidate (so still a prefix of the
+        // bucket in id order).  Else the next step scans the buckets.
+        {
+            const int nlow = L.nlow, njoin = L.njoin;
+            const bool ovf = nlow + njoin > kChunk;
+            const int cd = cnt_get(delta);
+            if (!ovf && nlow > 0) {
+                for (int i = tid; i < nlow; i += kT) {
+                    const int y = L.lj[i];
+                    int r = 0;
+                    for (int j = 0; j < nlow; ++j) r += L.lj[j] < y;
+                    L.nxt[r] = y;
+                }
+                if (tid == 0) {
+                    L.nnext = nlow;
+                    L.ndelta = delta - 1;
+                }
+            } else if (!ovf && cd > 0) {
+                const int rc = m - take;
+                const int* J = &L.lj[kChunk - njoin];
+                const int limit = rc + njoin == cd ? INT_MAX : L.cand[m - 1];
+                for (int i = tid; i < rc; i += kT) {
+                    const int r = L.cand[take + i];
+                    int c = 0;
+                    for (int j = 0; j < njoin; ++j) c += J[j] < limit && J[j] < r;
+                    if (i + c < kChunk) L.nxt[i + c] = r;
+                }
+                for (int i = tid; i < njoin; i += kT) {
+                    const int y = J[i];
+                    if (y >= limit) continue;
+                    int a = take, hi = m;
+                    while (a < hi) {
+                        const int mid = (a + hi) >> 1;
+                        if (L.cand[mid] < y) a = mid + 1;
+                        else hi = mid;
+                    }
+                    int c = a - take;
+                    for (int j = 0; j < njoin; ++j) c += J[j] < limit && J[j] < y;
+                    if (c < kChunk) L.nxt[c] = y;
+                    atomicAdd(&L.njp, 1);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    L.nnext = min(rc + L.njp, kChunk);
+                    L.ndelta = delta;
+                }
+            } else if (tid == 0) {
+                L.nnext = 0;
             }
         }
         if (tid == 0) {
@@ -519,6 +645,7 @@ int gcolor_smallest_last(int32_t n, const int32_t* row_ptr, const int32_t* col_i
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int* deg = nullptr;
     int* hist = nullptr;
+    int* longs = nullptr;
     PeelCtl* ctl = nullptr;
     u64* bm = nullptr;
     int* cnt = nullptr;
@@ -528,17 +655,22 @@ int gcolor_smallest_last(int32_t n, const int32_t* row_ptr, const int32_t* col_i
     Buckets b{};
     long long words = 0;
     int dcap = 0;
-    // hist[0..kDegCap]: degree counts; hist[kDegCap + 1]: the malformed-CSR flag
-    if (hipMalloc(&deg, sizeof(int) * (size_t)n) != hipSuccess || hipMalloc(&hist, sizeof(int) * (kDegCap + 2)) != hipSuccess ||
+    // hist[0..kDegCap]: degree counts; hist[kDegCap + 1]: the malformed-CSR
+    // flag; hist[kDegCap + 2]: the number of long rows listed in longs
+    if (hipMalloc(&deg, sizeof(int) * (size_t)n) != hipSuccess || hipMalloc(&hist, sizeof(int) * (kDegCap + 3)) != hipSuccess ||
+        hipMalloc(&longs, sizeof(int) * (size_t)n) != hipSuccess ||
         hipMalloc(&ctl, sizeof(PeelCtl)) != hipSuccess) {
         rc = GCOLOR_EHIP;
         goto done;
     }
-    if (hipMemsetAsync(hist, 0, sizeof(int) * (kDegCap + 2), st) != hipSuccess) {
+    if (hipMemsetAsync(hist, 0, sizeof(int) * (kDegCap + 3), st) != hipSuccess) {
         rc = GCOLOR_EHIP;
         goto done;
     }
-    k_peel_init<<<grid_for(n), 256, 0, st>>>(n, row_ptr, col_idx, deg, rank, hist, hist + kDegCap + 1);
+    k_peel_init<<<grid_for(n), 256, 0, st>>>(n, row_ptr, col_idx, deg, rank, hist, hist + kDegCap + 1, longs,
+                                             hist + kDegCap + 2);
+    k_peel_long<<<grid_for((long long)n * 4), 256, 0, st>>>(n, row_ptr, col_idx, deg, hist, hist + kDegCap + 1, longs,
+                                                            hist + kDegCap + 2);
     if (hipMemcpyAsync(h.data(), hist, sizeof(int) * (kDegCap + 2), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         rc = GCOLOR_EHIP;
@@ -591,6 +723,7 @@ done:
     if (bm) (void)hipFree(bm);
     if (cnt) (void)hipFree(cnt);
     if (deg) (void)hipFree(deg);
+    if (longs) (void)hipFree(longs);
     if (hist) (void)hipFree(hist);
     if (ctl) (void)hipFree(ctl);
     return rc;
