@@ -127,8 +127,9 @@ size_t gcolor_workspace_bytes(int32_t n, int64_t nnz);
 
 /*
  * Colour the graph.  Uses a workspace the library allocates on first use and
- * keeps per device (grown when a larger graph arrives).  Returns 0 or a
- * negative GCOLOR_E* code.  Every colouring call also keeps a 256-byte pinned
+ * keeps per device (grown when a larger graph arrives); calls on that
+ * workspace from several host threads take turns (each holds its device's
+ * lock until it returns).  Returns 0 or a negative GCOLOR_E* code.  Every colouring call also keeps a 256-byte pinned
  * host buffer per calling host thread for its small read-backs (held until
  * the process ends).
  */
@@ -266,7 +267,8 @@ int gcolor_get_serial_tail(int32_t* max_vertices);
  *                 need not be sorted; priority may be NULL);
  *   block_size    1 .. 2048;
  *   workspace     device memory of gcolor_blocks_workspace_bytes(n) bytes, or
- *                 NULL for the library's cached per-device allocation;
+ *                 NULL for the library's cached per-device allocation (calls
+ *                 on it from several host threads take turns);
  *   stats         optional (host): rounds, largest colour, and the sum over
  *                 rounds of the degrees of the uncoloured vertices.
  * The CSR is not validated.  The process-wide round cap of

@@ -490,6 +490,10 @@ struct DevWs {
 };
 std::mutex g_mu;
 std::vector<DevWs> g_ws;
+// Calls on the library's workspace hold their device's lock until they
+// return (concurrent host threads take turns on the one buffer).
+constexpr int kMaxDevices = 64;
+std::mutex g_call_mu[kMaxDevices];
 
 int blk_workspace(int dev, size_t need, void** out) {
     std::lock_guard<std::mutex> g(g_mu);
@@ -582,9 +586,12 @@ int color_graph_blocks(int32_t n, const int32_t* row_ptr, const int32_t* col_idx
     BLK_CHECK(hipGetDevice(&dev));
     const BlkLayout L = blk_layout(n);
     void* ws = workspace;
+    std::unique_lock<std::mutex> call;
     if (ws) {
         if (ws_bytes < L.total) return GCOLOR_EWORKSPACE;
     } else {
+        if (dev < 0 || dev >= kMaxDevices) return GCOLOR_ENOTSUP;
+        call = std::unique_lock<std::mutex>(g_call_mu[dev]);
         const int rc = blk_workspace(dev, L.total, &ws);
         if (rc) return rc;
     }

@@ -81,6 +81,8 @@ constexpr int kBins = 5;
 constexpr int kSets = 6;          // list sets (plain: 0,1 worklist ping-pong; incremental: see below)
 constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
 constexpr int kLogW = 5;          // int64 words per logged round
+constexpr int kSeedBlocksPerCu = 16;  // workgroups per CU of the seed kernels
+constexpr int kSumShift = 9;      // dirty-bitmap summary: one flag per 512 words (16384 vertices)
 
 // Vertices covered by one block-sized chunk of each bin.
 __host__ __device__ constexpr int chunk_vertices(int b) {
@@ -143,6 +145,8 @@ struct Args {
     int tail;
     const uint32_t* __restrict__ key;  // the priority array (NULL: natural)
     int* __restrict__ bcnt;            // (incremental) per-block bin counts of the dirty-list build
+    unsigned char* __restrict__ dsum;  // (incremental) per dirty bitmap: a flag per kSumWords-word region with a mark
+    int nregions;                      // regions per bitmap
 };
 
 struct Stage {
@@ -646,6 +650,10 @@ __device__ __forceinline__ unsigned* dbits(const Args& a, int k) {
     return a.dbits + (size_t)dlist(k) * (size_t)a.nwords;
 }
 
+__device__ __forceinline__ unsigned char* dsum(const Args& a, int k) {
+    return a.dsum + (size_t)dlist(k) * (size_t)a.nregions;
+}
+
 __device__ __forceinline__ bool is_dirty(const unsigned* __restrict__ bits, int x) {
     return (bits[x >> 5] >> (x & 31)) & 1u;
 }
@@ -667,6 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
     }
     const int stride = gridDim.x * kBlock;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < 3 * a.nwords; i += stride) a.dbits[i] = 0u;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < 3 * a.nregions; i += stride) a.dsum[i] = 0;
     for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = base + (int)threadIdx.x;
         const bool ok = v < a.n;
@@ -1376,6 +1385,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // kernel's blocks: the previous kernel cleared them, not block 0 here,
         // so that no block adds before they are cleared
     }
+    {
+        // this round's lists are built: its bitmap's summary flags start
+        // over for round k+3 (marked by the commit kernel of round k+2)
+        unsigned char* sm = dsum(a, k);
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.nregions; i += gridDim.x * kBlock) sm[i] = 0;
+    }
     const int set = dlist(k);
     const int n4 = a.ctl->cnt[set][4];
     const WaveMap m = make_wave_map(a.ctl, set);
@@ -1482,6 +1497,7 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
                                           int k, int v, int t, int start, int e) {
     constexpr int U = 8;
     unsigned* nbits = dbits(a, k + 1);
+    unsigned char* nsum = dsum(a, k + 1);
     for (int p0 = start; p0 < e; p0 += U * STRIDE) {
         int u[U], su[U];
 #pragma unroll
@@ -1504,7 +1520,10 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
         for (int j = 0; j < U; ++j) setm |= ((word[j] >> (u[j] & 31)) & 1u ? 0u : 1u) << j;
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            if (setm >> j & 1u) atomicOr(&nbits[u[j] >> 5], 1u << (u[j] & 31));
+            if (setm >> j & 1u) {
+                atomicOr(&nbits[u[j] >> 5], 1u << (u[j] & 31));
+                nsum[u[j] >> (5 + kSumShift)] = 1;
+            }
     }
 }
 
@@ -1697,6 +1716,19 @@ __host__ __device__ inline int compact_blocks(int nwords) {
     return b < 1 ? 1 : (b > kCompactMaxBlocks ? kCompactMaxBlocks : b);
 }
 
+// Whether the workgroup's bitmap words hold any mark (the summary flags of
+// the regions they overlap; a flag is set with every new mark).
+__device__ __forceinline__ bool block_has_marks(const Args& a, int kk) {
+    const int G = gridDim.x;
+    const int per_block = (a.nwords + G - 1) / G;
+    const int b0 = blockIdx.x * per_block, b1 = min(a.nwords, b0 + per_block);
+    if (b0 >= b1) return false;
+    const unsigned char* sm = dsum(a, kk);
+    bool any = false;
+    for (int r = b0 >> kSumShift; r <= (b1 - 1) >> kSumShift; ++r) any |= sm[r] != 0;
+    return any;
+}
+
 // This thread's slice of bitmap words.
 __device__ __forceinline__ void compact_slice(int nwords, int* w0, int* w1) {
     const int G = gridDim.x;
@@ -1732,6 +1764,10 @@ __global__ __launch_bounds__(kBlock) void k_dcount(Args a, int kk) {
     __shared__ int part[kWaves][kBins];
     const long long left = (long long)a.n - (long long)a.ctl->committed;
     if (left == 0 || (a.tail > 0 && left <= a.tail)) return;  // nothing to list
+    if (!block_has_marks(a, kk)) {  // block-uniform: no mark in these words
+        if (threadIdx.x < kBins) a.bcnt[blockIdx.x * 8 + threadIdx.x] = 0;
+        return;
+    }
     const unsigned* bits = dbits(a, kk);
     int w0, w1;
     compact_slice(a.nwords, &w0, &w1);
@@ -1756,6 +1792,9 @@ __global__ __launch_bounds__(kBlock) void k_dwrite(Args a, int kk) {
     const long long left = (long long)a.n - (long long)a.ctl->committed;
     if (left == 0 || (a.tail > 0 && left <= a.tail)) return;  // the list stays empty
     const int set = dlist(kk);
+    // no mark in these words: nothing to write (the last workgroup still
+    // writes the list totals)
+    if (blockIdx.x != gridDim.x - 1 && !block_has_marks(a, kk)) return;
     const unsigned* bits = dbits(a, kk);
     // offsets: the counts of the workgroups before this one (and, for the
     // last workgroup, the list totals)
@@ -1804,13 +1843,16 @@ __global__ __launch_bounds__(kBlock) void k_dwrite(Args a, int kk) {
         for (int q = 0; q < (int)threadIdx.x / kWave; ++q) before += wsum[q][b];
         off[b] += before;
     }
+    int* dsts[kBins];
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) dsts[b] = list_ptr(a, set, b);
     for (int w = w0; w < w1; ++w) {
         const unsigned x = bits[w];
         if (x == 0u) continue;
 #pragma unroll
         for (int b = 0; b < kBins; ++b) {
             unsigned y = x & bin_mask(a, w, b);
-            int* dst = list_ptr(a, set, b);
+            int* dst = dsts[b];
             int o = off[b];
             while (y) {
                 dst[o++] = w * 32 + __builtin_ctz(y);
@@ -2317,8 +2359,14 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, colp, hid, hrow, hF, act, total;
+    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, dsum, colp, hid, hrow, hF, act, total;
 };
+
+// Summary regions of a dirty bitmap of n bits (one flag per 2^kSumShift words).
+int sum_regions(int32_t n) {
+    const int64_t words = ((int64_t)n + 31) / 32;
+    return (int)((words + (1 << kSumShift) - 1) >> kSumShift) + 1;
+}
 
 Layout layout(int32_t n, int64_t nnz) {
     Layout L;
@@ -2335,6 +2383,7 @@ Layout layout(int32_t n, int64_t nnz) {
     L.dbits = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.bplane = off; off += align_up(sizeof(uint32_t) * 3 * (((size_t)n + 31) / 32));
     L.bcnt = off;  off += align_up(sizeof(int32_t) * 8 * (size_t)kCompactMaxBlocks);
+    L.dsum = off;  off += align_up(3 * (size_t)sum_regions(n));
     L.colp = off;  off += align_up(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     // rows of degree > kHeavyDeg: at most nnz / (kHeavyDeg + 1) of them
     const size_t nh = (size_t)(nnz > 0 ? nnz : 0) / (kHeavyDeg + 1) + 1;
@@ -2354,6 +2403,11 @@ struct DeviceCache {
 
 std::mutex g_mu;
 std::vector<DeviceCache> g_dev;
+// Calls on the library's workspace hold their device's lock from the
+// workspace lookup to their return, so that concurrent host threads take
+// turns instead of sharing (or freeing) one buffer.
+constexpr int kMaxDevices = 64;
+std::mutex g_call_mu[kMaxDevices];
 
 // Process-wide tuning: degree-bin limits and blocks per CU of the grids.
 int g_bins[4] = {8, 32, 128, 2048};
@@ -2568,9 +2622,9 @@ int inc_rounds(const Args& a, int64_t limit, const int* grid, Launcher& L, int32
 
 // Dataflow rounds in batches between host checks (the batch grows to 256
 // rounds: a natural-order graph can need tens of thousands).
-int run_dataflow(const Args& a, int64_t n, int64_t limit, int vgrid, int grid, bool natural, Launcher& L,
+int run_dataflow(const Args& a, int64_t n, int64_t limit, int vgrid, int sgrid, int grid, bool natural, Launcher& L,
                  int32_t* host, hipStream_t st) {
-    k_flow_seed<<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    k_flow_seed<<<sgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
     int64_t k = 1;
     int batch = 4;
@@ -2742,10 +2796,10 @@ __global__ void k_async_finish(const Ctl* ctl, const long long* __restrict__ log
 // a signed byte: the engine starts with 8-bit state words (half the bytes of
 // the gathers that dominate every kernel) and, if round 128 is reached,
 // widens them to 16 bits (32 when max degree + 1 exceeds 32767).
-int run_incremental(Args a, int64_t n, int64_t limit, int vgrid, const int* grid, bool natural, void* wide_slot,
+int run_incremental(Args a, int64_t n, int64_t limit, int vgrid, int sgrid, const int* grid, bool natural, void* wide_slot,
                     Launcher& L, int32_t* host, hipStream_t st) {
     constexpr int kLast8 = 127;
-    k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    k_inc_seed<int8_t><<<sgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     GC_CHECK(hipGetLastError());
     int width = 1;  // bytes of the state words when the rounds end
     if (a.tail < n) {  // with a sequential finish of every vertex there is no round
@@ -2820,6 +2874,8 @@ Args make_args(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* co
     a.tail = 0;
     a.key = nullptr;
     a.bcnt = reinterpret_cast<int*>(base + Lw.bcnt);
+    a.dsum = reinterpret_cast<unsigned char*>(base + Lw.dsum);
+    a.nregions = sum_regions(n);
 
     return a;
 }
@@ -2861,6 +2917,9 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     }
 
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    // the seed kernels wait on binary searches of the rows: more workgroups
+    // in flight than the round kernels use
+    const int sgrid = std::max(1, std::min(cus * kSeedBlocksPerCu, (n + kBlock - 1) / kBlock));
     k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         // rows reordered so that the neighbours preceding v come first
@@ -2884,9 +2943,9 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         }
         rc = run_plain(a, limit, grid, L, host, st);
     } else if (flow) {
-        rc = run_dataflow(a, n, limit, vgrid, grid, natural, L, host, st);
+        rc = run_dataflow(a, n, limit, vgrid, sgrid, grid, natural, L, host, st);
     } else {
-        rc = run_incremental(a, n, limit, vgrid, kgrid, natural, base + Lw.told, L, host, st);
+        rc = run_incremental(a, n, limit, vgrid, sgrid, kgrid, natural, base + Lw.told, L, host, st);
     }
     if (rc) return rc;
 
@@ -2995,6 +3054,9 @@ int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
     Args a = make_args(n, nnz, row_ptr, col_idx, colors, base, Lw, ctl, log);
     const bool natural = priority == nullptr;
     const int vgrid = std::max(1, std::min(grid, (n + kBlock - 1) / kBlock));
+    // the seed kernels wait on binary searches of the rows: more workgroups
+    // in flight than the round kernels use
+    const int sgrid = std::max(1, std::min(cus * kSeedBlocksPerCu, (n + kBlock - 1) / kBlock));
     k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         int* colp = reinterpret_cast<int*>(base + Lw.colp);
@@ -3004,7 +3066,7 @@ int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
         a.colp = colp;
     }
     constexpr int kLast8 = 127;
-    k_inc_seed<int8_t><<<vgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
+    k_inc_seed<int8_t><<<sgrid, kBlock, 0, st>>>(a, natural ? 1 : 0);
     k_inc_c<int8_t><<<kgrid[1], kBlock, 0, st>>>(a, 1);
     GC_CHECK(launch_dirty_lists(a, 2, st));
     int k = 2;
@@ -3103,9 +3165,13 @@ int color_graph_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, co
     void* ws = workspace;
     if (ws) {
         if (ws_bytes < need) return GCOLOR_EWORKSPACE;
-    } else {
+    }
+    std::unique_lock<std::mutex> call;
+    if (!ws) {
         int dev = 0;
         GC_CHECK(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices) return GCOLOR_ENOTSUP;
+        call = std::unique_lock<std::mutex>(g_call_mu[dev]);
         rc = library_workspace(dev, need, &ws);
         if (rc) return rc;
     }
