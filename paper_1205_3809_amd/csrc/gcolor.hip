@@ -152,6 +152,7 @@ struct Args {
 struct Stage {
     int cnt[kBins];
     int base[kBins];
+    int off[kBins];  // bin offsets inside a list set (from the bin populations)
     int q[kStageTotal];
 };
 
@@ -171,6 +172,16 @@ __device__ __forceinline__ int bin_offset(const Ctl* ctl, int b) {
 
 __device__ __forceinline__ int* list_ptr(const Args& a, int set, int b) {
     return a.lists + (size_t)set * (size_t)a.n + bin_offset(a.ctl, b);
+}
+
+// All bin offsets at once (four independent loads, issued together).
+__device__ __forceinline__ void bin_offsets(const Ctl* ctl, int* off) {
+    const int p0 = ctl->binpop[0], p1 = ctl->binpop[1], p2 = ctl->binpop[2], p3 = ctl->binpop[3];
+    off[0] = 0;
+    off[1] = p0;
+    off[2] = p0 + p1;
+    off[3] = p0 + p1 + p2;
+    off[4] = p0 + p1 + p2 + p3;
 }
 
 template <int GS>
@@ -212,6 +223,7 @@ constexpr int kWStageTotal = 992;
 struct WaveStage {
     int cnt[kBins];
     int base[kBins];
+    int off[kBins];  // bin offsets inside a list set (from the bin populations)
     int q[kWStageTotal];
 };
 
@@ -227,8 +239,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void stage_init(Stage* st) {
-    if (threadIdx.x < kBins) st->cnt[threadIdx.x] = 0;
+__device__ __forceinline__ void stage_init(const Args& a, Stage* st) {
+    if (threadIdx.x < kBins) {
+        st->cnt[threadIdx.x] = 0;
+        st->off[threadIdx.x] = bin_offset(a.ctl, threadIdx.x);
+    }
     __syncthreads();
 }
 
@@ -256,7 +271,7 @@ __device__ __forceinline__ void stage_append(const Args& a, ST* st, bool pred, i
                 st->q[soff(st, k) + slot] = v;
             } else {
                 const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
-                list_ptr(a, set, k)[g] = v;
+                a.lists[(size_t)set * (size_t)a.n + st->off[k] + g] = v;
             }
         }
     }
@@ -272,7 +287,7 @@ __device__ __forceinline__ void stage_push(const Args& a, ST* st, int v, int deg
         st->q[soff(st, k) + slot] = v;
     } else {
         const int g = atomicAdd(&a.ctl->cnt[set][k], 1);
-        list_ptr(a, set, k)[g] = v;
+        a.lists[(size_t)set * (size_t)a.n + st->off[k] + g] = v;
     }
 }
 
@@ -283,8 +298,11 @@ __device__ __forceinline__ void stage_append_lookup(const Args& a, ST* st, bool 
 }
 
 // Per-wavefront stage: clear (wave-uniform call).
-__device__ __forceinline__ void wstage_init(WaveStage* st) {
-    if (__lane_id() < kBins) st->cnt[__lane_id()] = 0;
+__device__ __forceinline__ void wstage_init(const Args& a, WaveStage* st) {
+    if (__lane_id() < kBins) {
+        st->cnt[__lane_id()] = 0;
+        st->off[__lane_id()] = bin_offset(a.ctl, __lane_id());
+    }
     wave_sync();
 }
 
@@ -300,7 +318,7 @@ __device__ __forceinline__ void wstage_flush(const Args& a, WaveStage* st, int s
     wave_sync();
 #pragma unroll
     for (int b = 0; b < kBins; ++b) {
-        int* dst = list_ptr(a, set, b) + st->base[b];
+        int* dst = a.lists + (size_t)set * (size_t)a.n + st->off[b] + st->base[b];
         for (int i = lane; i < st->cnt[b]; i += kWave) dst[i] = st->q[wstage_off(b) + i];
     }
     wave_sync();
@@ -329,7 +347,7 @@ __device__ __forceinline__ void stage_flush(const Args& a, Stage* st, int set) {
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < kBins; ++b) {
-        int* dst = list_ptr(a, set, b) + st->base[b];
+        int* dst = a.lists + (size_t)set * (size_t)a.n + st->off[b] + st->base[b];
         for (int i = threadIdx.x; i < st->cnt[b]; i += blockDim.x) dst[i] = st->q[stage_off(b) + i];
     }
     __syncthreads();
@@ -595,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
     __shared__ Stage st;
     const ChunkMap m = make_map(a.ctl, side);
     if ((int)blockIdx.x >= m.total) return;
-    stage_init(&st);
+    stage_init(a, &st);
     const int nside = side ^ 1;
     long long ework = 0;
 #define P2_GS(GS, L, C, LOC) phase2_chunk<GS>(a, &st, L, C, LOC, nside, &ework)
@@ -665,7 +683,7 @@ template <typename S>
 __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
     __shared__ Stage stg;
     if (a.ctl->err) return;  // the CSR failed validation: nothing is read
-    stage_init(&stg);
+    stage_init(a, &stg);
     S* st = static_cast<S*>(a.st);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int t = 0; t < kSets; ++t)
@@ -1402,15 +1420,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // every bit of that bitmap belongs to a previous dirty vertex, so the
         // words holding them can be zeroed whole
         unsigned* pbits = dbits(a, k - 1);
+        int off[kBins];
+        bin_offsets(a.ctl, off);
         for (int b = 0; b < kBins; ++b) {
             const int c = a.ctl->cnt[dlist(k - 1)][b];
-            const int* l = list_ptr(a, dlist(k - 1), b);
+            const int* l = a.lists + (size_t)dlist(k - 1) * (size_t)a.n + off[b];
             for (int i = blockIdx.x * kBlock + threadIdx.x; i < c; i += gridDim.x * kBlock) pbits[l[i] >> 5] = 0u;
         }
     }
     const int cs = cset(k);
     WaveStage* stg = &wstg[threadIdx.x / kWave];
-    wstage_init(stg);
+    wstage_init(a, stg);
     long long dedges[2] = {0, 0};  // degree sum and scanned entries of the dirty rows
     const int* l4 = list_ptr(a, set, 4);
     for (int c = blockIdx.x; c < n4; c += gridDim.x) {
@@ -1844,8 +1864,12 @@ __global__ __launch_bounds__(kBlock) void k_dwrite(Args a, int kk) {
         off[b] += before;
     }
     int* dsts[kBins];
+    {
+        int off[kBins];
+        bin_offsets(a.ctl, off);
 #pragma unroll
-    for (int b = 0; b < kBins; ++b) dsts[b] = list_ptr(a, set, b);
+        for (int b = 0; b < kBins; ++b) dsts[b] = a.lists + (size_t)set * (size_t)a.n + off[b];
+    }
     for (int w = w0; w < w1; ++w) {
         const unsigned x = bits[w];
         if (x == 0u) continue;
@@ -2015,7 +2039,7 @@ __device__ __forceinline__ void flow_block(const Args& a, Stage* stg, int k, int
 // split is found here by binary search in the sorted row).
 __global__ __launch_bounds__(kBlock) void k_flow_seed(Args a, int natural) {
     __shared__ Stage stg;
-    stage_init(&stg);
+    stage_init(a, &stg);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int i = 0; i < kLogW; ++i) a.log[i] = 0;
     const int stride = gridDim.x * kBlock;
@@ -2066,7 +2090,7 @@ __global__ __launch_bounds__(kBlock) void k_flow(Args a, int k) {
         }
     }
     if ((int)blockIdx.x >= m.total) return;
-    stage_init(&stg);
+    stage_init(a, &stg);
     long long ncol = 0, work = 0;
     const int ns = fset(k + 1);
 #define F_GS(GS, L, C, LOC) flow_chunk<GS>(a, &stg, k, L, C, LOC, &ncol, &work)
@@ -2098,7 +2122,7 @@ __global__ __launch_bounds__(kBlock) void k_maxdeg(int n, const int* __restrict_
 // are the prefix below v; split[v] = lower_bound(row, v) - row start.
 __global__ __launch_bounds__(kBlock) void k_setup_natural(Args a, int* split) {
     __shared__ Stage st;
-    stage_init(&st);
+    stage_init(a, &st);
     const int stride = gridDim.x * kBlock;
     for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = base + (int)threadIdx.x;
@@ -2147,7 +2171,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_pop(Args a) {
 __global__ __launch_bounds__(kBlock) void k_setup_bins(Args a) {
     __shared__ Stage st;
     if (a.ctl->err) return;  // the CSR failed validation: nothing is read
-    stage_init(&st);
+    stage_init(a, &st);
     const int stride = gridDim.x * kBlock;
     for (int base = blockIdx.x * kBlock; base < a.n; base += stride) {
         const int v = base + (int)threadIdx.x;
@@ -2269,7 +2293,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Args a, const int* __restric
     for (int c = blockIdx.x; c < m.total; c += gridDim.x) {
         const int b = chunk_bin(m, c);
         const int local = c - m.start[b];
-        const int* list = list_ptr(a, 0, b);
+        const int* list = a.lists + pick5(m.off, b);
         switch (b) {
             case 0: reorder_chunk<1>(a, col, out, split, key, list, m.cnt[0], local); break;
             case 1: reorder_chunk<4>(a, col, out, split, key, list, m.cnt[1], local); break;
@@ -2920,7 +2944,7 @@ int run_coloring(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
     // the seed kernels wait on binary searches of the rows: more workgroups
     // in flight than the round kernels use
     const int sgrid = std::max(1, std::min(cus * kSeedBlocksPerCu, (n + kBlock - 1) / kBlock));
-    k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
+    k_bin_pop<<<sgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         // rows reordered so that the neighbours preceding v come first
         int* colp = reinterpret_cast<int*>(base + Lw.colp);
@@ -3057,7 +3081,7 @@ int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
     // the seed kernels wait on binary searches of the rows: more workgroups
     // in flight than the round kernels use
     const int sgrid = std::max(1, std::min(cus * kSeedBlocksPerCu, (n + kBlock - 1) / kBlock));
-    k_bin_pop<<<vgrid, kBlock, 0, st>>>(a);
+    k_bin_pop<<<sgrid, kBlock, 0, st>>>(a);
     if (!natural) {
         int* colp = reinterpret_cast<int*>(base + Lw.colp);
         k_setup_bins<<<vgrid, kBlock, 0, st>>>(a);
