@@ -24,9 +24,11 @@
 //    Tentative colours of other vertices cannot change (their forbidden sets
 //    only grew by colours they do not hold), so rounds are the plain engine's,
 //    vertex for vertex.  Kernels per round: k_inc_a (first-fit of dirty
-//    vertices, counter recount and updates, candidate list) and k_inc_c
-//    (counters completed for dirty vertices with dirty preceding neighbours,
-//    commit of candidates whose counter is 0, dirty marks to neighbours).
+//    vertices, counter recount and updates, candidate list, and for a dirty
+//    vertex with dirty preceding neighbours the list of those neighbours) and
+//    k_inc_c (counters completed for dirty vertices with dirty preceding
+//    neighbours, from those lists or by rescanning the row, commit of
+//    candidates whose counter is 0, dirty marks to neighbours).
 //    A vertex's state word holds its tentative colour while it is uncoloured
 //    and minus its colour once committed, so one gather of a neighbour's word
 //    answers both "committed, with which colour" and "same tentative colour".
@@ -83,6 +85,11 @@ constexpr int kMaxLog = 1 << 16;  // rounds recorded in the device log
 constexpr int kLogW = 5;          // int64 words per logged round
 constexpr int kSeedBlocksPerCu = 16;  // workgroups per CU of the seed kernels
 constexpr int kSumShift = 9;      // dirty-bitmap summary: one flag per 512 words (16384 vertices)
+// Pair lists: a start below 2^kPairShift and a count below 2^(31 - kPairShift)
+// packed into one non-negative int.
+constexpr int kPairShift = 24;
+constexpr int kPairMaxCap = 1 << kPairShift;
+constexpr int kPairMaxCount = (1 << (31 - kPairShift)) - 1;
 
 // Vertices covered by one block-sized chunk of each bin.
 __host__ __device__ constexpr int chunk_vertices(int b) {
@@ -147,6 +154,13 @@ struct Args {
     int* __restrict__ bcnt;            // (incremental) per-block bin counts of the dirty-list build
     unsigned char* __restrict__ dsum;  // (incremental) per dirty bitmap: a flag per kSumWords-word region with a mark
     int nregions;                      // regions per bitmap
+    // (incremental) dirty preceding neighbours of the dirty vertices whose
+    // counter the commit kernel completes: pref[w] = start in pbuf | count
+    // << kPairShift, or -1 (the commit kernel then rescans w's preceding
+    // entries); pbuf holds pcap ids, an equal region per wavefront
+    int* __restrict__ pref;
+    int* __restrict__ pbuf;
+    int pcap;
 };
 
 struct Stage {
@@ -224,6 +238,7 @@ struct WaveStage {
     int cnt[kBins];
     int base[kBins];
     int off[kBins];  // bin offsets inside a list set (from the bin populations)
+    int pbase, pfill, plen;  // (dirty-vertex kernel) this wavefront's pair region: start, used, size
     int q[kWStageTotal];
 };
 
@@ -882,16 +897,56 @@ __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __rest
 }
 
 
+// Pair list of a dirty vertex w with dirty preceding neighbours (wavefront
+// tier, row in registers: ids xs, the dirty preceding ones in the slots of
+// dpm): its group's lanes write those neighbours into the wavefront's region
+// of the pair buffer, at offsets from a wavefront-wide prefix over the active
+// lanes (counts up to kCache: four ballots), and lane 0 of the group stores
+// the list's start and length in pref[w].  A list that does not fit the
+// region (or is longer than kPairMaxCount) is stored as -1: the commit kernel
+// then rescans w's preceding entries.  Every active lane of the wavefront
+// calls this.
+template <int GS>
+__device__ __forceinline__ void pair_list(const Args& a, WaveStage* stg, int w, const int* xs, unsigned dpm) {
+    static_assert(kCache < 16, "counts fit four ballots");
+    const int mine = __popc(dpm);
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t m = __ballot((mine >> q) & 1);
+        pre += __popcll(m & __lanemask_lt()) << q;
+        tot += __popcll(m) << q;
+    }
+    if (tot == 0) return;  // wavefront-uniform
+    const int fill = stg->pfill;
+    const bool fits = fill + tot <= stg->plen;
+    const int at = stg->pbase + fill + pre;
+    if (fits && mine) {
+        int i = 0;
+#pragma unroll
+        for (int j = 0; j < kCache; ++j)
+            if (dpm >> j & 1u) a.pbuf[at + i++] = xs[j];
+    }
+    const int gtot = group_sum<GS>(mine);
+    const int gat = __shfl(at, __lane_id() & ~(GS - 1));
+    if (gtot > 0 && (__lane_id() & (GS - 1)) == 0)
+        a.pref[w] = fits && gtot <= kPairMaxCount ? gat | (gtot << kPairShift) : -1;
+    wave_sync();  // every lane has read pfill
+    if (fits && __lane_id() == __ffsll((unsigned long long)__ballot(true)) - 1) stg->pfill = fill + tot;
+    wave_sync();
+}
+
 // inc_a_eval over N entries of dirty vertex w held in registers (ids xs,
 // words sv, at positions start, start + GS, ...; preceding below lim), in
 // stages over all of them: every bitmap read, then every counter atomic,
 // then the rare flag exchanges, so that a lane keeps its reads and atomics
 // in flight together instead of waiting on each entry in turn.  Positions
-// from e on hold w itself and are skipped.
-template <int GS, int N>
+// from e on hold w itself and are skipped.  *dpm collects the slots j that
+// hold a dirty preceding neighbour; with LIST they also form w's pair list.
+template <int GS, int N, bool LIST = false>
 __device__ __forceinline__ void inc_a_eval_staged(const Args& a, WaveStage* stg, const unsigned* __restrict__ bits, int k,
                                                   int w, int start, int e, int lim, int now, int old, const int* xs,
-                                                  const int* sv, int* cnt, bool* dlow) {
+                                                  const int* sv, int* cnt, bool* dlow, unsigned* dpm) {
     // which entries need their dirty bit: uncommitted preceding neighbours,
     // and later ones (not w) holding now or old
     unsigned need = 0u;
@@ -913,13 +968,18 @@ __device__ __forceinline__ void inc_a_eval_staged(const Args& a, WaveStage* stg,
         const int sx = sv[j];
         const bool dirty = (word[j] >> (xs[j] & 31)) & 1u;
         if (p < lim) {
-            if (sx > 0 && dirty) *dlow = true;
-            else *cnt += (sx == now);
+            if (sx > 0 && dirty) {
+                *dlow = true;
+                *dpm |= 1u << j;
+            } else {
+                *cnt += (sx == now);
+            }
         } else if ((need >> j & 1u) && !dirty) {
             if (sx == now) addm |= 1u << j;
             else subm |= 1u << j;
         }
     }
+    if constexpr (LIST) pair_list<GS>(a, stg, w, xs, *dpm);
     int r[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -1104,7 +1164,8 @@ __device__ __forceinline__ void inc_a_heavy(const Args& a, WaveStage* stg, int k
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) sx[j] = st[x[j]];
-        inc_a_eval_staged<GS, 4>(a, stg, bits, k, w, qb + lig, len, hv.pa, now, old, x, sx, &cnt, &dlow);
+        unsigned dpm = 0u;
+        inc_a_eval_staged<GS, 4>(a, stg, bits, k, w, qb + lig, len, hv.pa, now, old, x, sx, &cnt, &dlow, &dpm);
         if (compact) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1174,11 +1235,12 @@ __device__ __forceinline__ void inc_a_pass2_gather(const Args& a, WaveStage* stg
 // Dirty vertex w handled by a group of GS lanes (GS = kBlock: the whole
 // workgroup, with LDS for the reductions).  Returns via the stage: w itself
 // to the candidate list, as ~w while preceding dirty neighbours leave its
-// count open, as w when the count is final and 0.
+// count open, as w when the count is final and 0.  A ~w of the wavefront
+// tier whose row did not sit in registers (listed false) gets no pair list.
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
-                                             long long* dedges);
+                                             long long* dedges, bool listed = false);
 
 // What a dirty vertex's processing reads first: its id, row bounds, split
 // point and state word.  The wavefront walk loads it one chunk ahead (no
@@ -1278,20 +1340,23 @@ __device__ __forceinline__ void inc_a_vertex_pre(const Args& a, WaveStage* stg, 
     // counters
     int cnt = 0;
     bool dlow = false;
+    unsigned dpm = 0u;
     if (cached) {
-        inc_a_eval_staged<GS, kCache>(a, stg, bits, k, w, s + lig, e, lim, now, old, xs, sv, &cnt, &dlow);
+        inc_a_eval_staged<GS, kCache, GS <= kWave>(a, stg, bits, k, w, s + lig, e, lim, now, old, xs, sv, &cnt,
+                                                   &dlow, &dpm);
     } else {
         inc_a_pass2_gather<GS, S>(a, stg, st, bits, k, w, s + lig, e, lim, now, old, &cnt, &dlow);
     }
-    inc_a_finish<GS, S>(a, stg, k, w, e - s, e - s, lig, now, cnt, dlow, shc, dedges);
+    inc_a_finish<GS, S>(a, stg, k, w, e - s, e - s, lig, now, cnt, dlow, shc, dedges, cached);
 }
+
 
 // Group totals of the counter and the preceding-dirty flag; state, counter
 // and list appends of dirty vertex w.
 template <int GS, typename S>
 __device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int k, int w, int deg,
                                              int scanned, int lig, int now, int cnt, bool dlow, int* shc,
-                                             long long* dedges) {
+                                             long long* dedges, bool listed) {
     S* st = static_cast<S*>(a.st);
     const int cs = cset(k);
     int dl = dlow ? 1 : 0;
@@ -1309,6 +1374,9 @@ __device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int 
     } else {
         cnt = group_sum<GS>(cnt);
         dl = group_sum<GS>(dl);
+        // the commit kernel reads pref[w] of every ~w of bins 0..3 (a row
+        // in registers had its list stored by the staged evaluation)
+        if (!listed && dl > 0 && lig == 0) a.pref[w] = -1;
     }
     bool to_b = false, cand = false;
     if (lig == 0) {
@@ -1431,6 +1499,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int cs = cset(k);
     WaveStage* stg = &wstg[threadIdx.x / kWave];
     wstage_init(a, stg);
+    if (__lane_id() == 0) {  // this wavefront's region of the pair buffer
+        const int waves = gridDim.x * kWaves;
+        stg->plen = a.pcap / waves;
+        stg->pbase = (blockIdx.x * kWaves + (int)threadIdx.x / kWave) * stg->plen;
+        stg->pfill = 0;
+    }
+    wave_sync();
     long long dedges[2] = {0, 0};  // degree sum and scanned entries of the dirty rows
     const int* l4 = list_ptr(a, set, 4);
     for (int c = blockIdx.x; c < n4; c += gridDim.x) {
@@ -1554,7 +1629,7 @@ __device__ __forceinline__ void inc_c_row(const Args& a, const int* __restrict__
 // split point, counter) comes preloaded: only the entry's own group writes
 // those words of v in this kernel.
 struct CInfo {
-    int ent, t, s, e, sp, conf;
+    int ent, t, s, e, sp, conf, pref;
 };
 
 template <typename S>
@@ -1568,10 +1643,34 @@ __device__ __forceinline__ CInfo load_cinfo(const Args& a, int ent) {
         r.e = a.row_ptr[v + 1];
         r.sp = a.split[v];
         r.conf = a.conf[v];
+        r.pref = ent < 0 ? a.pref[v] : -1;
     } else {
         r.t = r.s = r.e = r.sp = r.conf = 0;
+        r.pref = -1;
     }
     return r;
+}
+
+// Preceding dirty neighbours of w holding colour now, from w's pair list
+// (start and length packed in pr): the same neighbours, compared the same
+// way, as inc_b_count over the row.
+template <int STRIDE, typename S>
+__device__ __forceinline__ int pair_count(const Args& a, const S* __restrict__ st, int pr, int lig, int now) {
+    const int* __restrict__ q = a.pbuf + (pr & (kPairMaxCap - 1));
+    const int len = pr >> kPairShift;
+    int c = 0;
+    for (int i0 = lig; i0 < len; i0 += 4 * STRIDE) {
+        int x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = i0 + j * STRIDE < len ? q[i0 + j * STRIDE] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (x[j] >= 0) {
+                const int sx = st[x[j]];
+                c += ((sx < 0 ? -sx : sx) == now);
+            }
+    }
+    return c;
 }
 
 template <int GS, typename S>
@@ -1584,16 +1683,21 @@ __device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& c
     const int s = ci.s, e = ci.e;
     bool commit;
     if (ent < 0) {
-        const int* row = a.colp;
-        int lim = s + ci.sp;
-        if constexpr (GS == kWave) {
-            if (e - s > kHeavyDeg) {  // preceding segment of the active row
-                const HeavyView hv = heavy_view(a, v, s);
-                row = hv.row;
-                lim = s + hv.pa;
+        int c;
+        if (ci.pref >= 0) {  // group-uniform
+            c = group_sum<GS>(pair_count<GS, S>(a, st, ci.pref, lig, t));
+        } else {
+            const int* row = a.colp;
+            int lim = s + ci.sp;
+            if constexpr (GS == kWave) {
+                if (e - s > kHeavyDeg) {  // preceding segment of the active row
+                    const HeavyView hv = heavy_view(a, v, s);
+                    row = hv.row;
+                    lim = s + hv.pa;
+                }
             }
+            c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
         }
-        const int c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
         const int tot = ci.conf + c;
         if (lig == 0) a.conf[v] = tot;
         commit = tot == 0;
@@ -2383,8 +2487,12 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, dsum, colp, hid, hrow, hF, act, total;
+    size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, dsum, colp, hid, hrow, hF, act, pref,
+        pbuf, total;
 };
+
+// Entries of the pair buffer: one per vertex, at most kPairMaxCap.
+int pair_capacity(int32_t n) { return n < kPairMaxCap ? n : kPairMaxCap; }
 
 // Summary regions of a dirty bitmap of n bits (one flag per 2^kSumShift words).
 int sum_regions(int32_t n) {
@@ -2415,6 +2523,8 @@ Layout layout(int32_t n, int64_t nnz) {
     L.hrow = off;  off += align_up(sizeof(int4) * nh);
     L.hF = off;    off += align_up(sizeof(uint32_t) * kFW * nh);
     L.act = off;   off += align_up(sizeof(int32_t) * 2 * (size_t)(nnz > 0 ? nnz : 1));
+    L.pref = off;  off += align_up(vn);
+    L.pbuf = off;  off += align_up(sizeof(int32_t) * (size_t)pair_capacity(n));
     L.total = off;
     return L;
 }
@@ -2900,6 +3010,9 @@ Args make_args(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* co
     a.bcnt = reinterpret_cast<int*>(base + Lw.bcnt);
     a.dsum = reinterpret_cast<unsigned char*>(base + Lw.dsum);
     a.nregions = sum_regions(n);
+    a.pref = reinterpret_cast<int*>(base + Lw.pref);
+    a.pbuf = reinterpret_cast<int*>(base + Lw.pbuf);
+    a.pcap = pair_capacity(n);
 
     return a;
 }
