@@ -118,7 +118,8 @@ struct Ctl {
     unsigned long long committed;  // vertices committed so far
     int32_t nheavy;                // (incremental) rows with an active copy
     int32_t binpop[kBins];         // vertices whose degree falls in each bin
-    int32_t pad[4];
+    int32_t widened;               // (stream-ordered) the state words moved to 32 bits
+    int32_t pad[3];
 };
 static_assert(sizeof(Ctl) == 320, "ctl layout");
 
@@ -127,7 +128,7 @@ struct Args {
     const int* __restrict__ row_ptr;
     const int* __restrict__ colp;  // original col_idx, or the reordered copy
     int* __restrict__ split;       // entries at the front of each row that precede the vertex
-    int* __restrict__ color;       // the caller's colors_out: 0 until committed
+    int* __restrict__ color;       // the caller's colors_out (incremental engine: written after the rounds)
     int* __restrict__ tent;        // (plain) tentative colour
     void* st;                      // (incremental) state words, int8_t, int16_t or int32_t
     int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
@@ -651,7 +652,8 @@ __global__ __launch_bounds__(kBlock) void k_phase2(Args a, int side, int k) {
 //   st[v] > 0   v is uncoloured, st[v] is its tentative colour
 //   st[v] < 0   v is committed with colour -st[v]
 // so a single gather of a neighbour's word answers every question a kernel
-// asks about it.  colors_out is written once, at commit.
+// asks about it.  colors_out is written once, from the state words, after
+// the last round (k_inc_colors): the commits write only state words.
 //
 // Round k:
 //   k_inc_a  for each dirty vertex w (tentative colour must move): one scan
@@ -1717,7 +1719,6 @@ __device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& c
         }
         inc_c_row<GS, S>(a, row, st, k, v, t, start + lig, end);
         if (lig == 0) {
-            a.color[v] = t;
             st[v] = (S)(-t);
             *ncom += 1;
             *ndeg += e - s;
@@ -1762,7 +1763,6 @@ __device__ __forceinline__ void inc_c_block(const Args& a, int k, int ent, int* 
     inc_c_row<kBlock, S>(a, row, st, k, v, t, start + (int)threadIdx.x, end);
     __syncthreads();  // every thread has read st[v] before it is overwritten
     if (threadIdx.x == 0) {
-        a.color[v] = t;
         st[v] = (S)(-t);
         *ncom += 1;
         *ndeg += e - s;
@@ -2880,15 +2880,39 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_finish(Args a) {
     if (threadIdx.x == 0 && m > 0) atomicAdd((unsigned long long*)&a.ctl->committed, (unsigned long long)m);
 }
 
+// Output colours of the incremental engine, written once after the rounds
+// (the commits only write state words): minus the word of a committed vertex,
+// 0 for a vertex still uncoloured (left to the sequential finish).
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_inc_colors(int n, const S* __restrict__ st, int* __restrict__ color) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int x = st[v];
+        color[v] = x < 0 ? -x : 0;
+    }
+}
+
+// The same for the stream-ordered colouring, whose state words are 32-bit
+// from round 128 on only when round 128 had work (ctl->widened).
+__global__ __launch_bounds__(kBlock) void k_inc_colors_async(int n, const int8_t* __restrict__ narrow,
+                                                             const int32_t* __restrict__ wide, const Ctl* ctl,
+                                                             int* __restrict__ color) {
+    const bool w = ctl->widened != 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int x = w ? wide[v] : (int)narrow[v];
+        color[v] = x < 0 ? -x : 0;
+    }
+}
+
 // Stream-ordered colouring: the round count is not known to the host, so the
 // engine enqueues a fixed budget of rounds; a round whose dirty list is empty
 // finds no work and its blocks return at once.  The state widens (to int32)
 // before round 128 only when round 128 has work.
 __global__ __launch_bounds__(kBlock) void k_widen_if_busy(int n, const int8_t* __restrict__ src,
-                                                          int32_t* __restrict__ dst, const Ctl* ctl, int set) {
+                                                          int32_t* __restrict__ dst, Ctl* ctl, int set) {
     int busy = 0;
     for (int b = 0; b < kBins; ++b) busy += ctl->cnt[set][b];
     if (busy == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->widened = 1;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) dst[v] = (int32_t)src[v];
 }
 
@@ -2964,6 +2988,10 @@ int run_incremental(Args a, int64_t n, int64_t limit, int vgrid, int sgrid, cons
             if (rc) return rc;
         }
     }
+    if (width == 1) k_inc_colors<int8_t><<<vgrid, kBlock, 0, st>>>((int)n, static_cast<const int8_t*>(a.st), a.color);
+    else if (width == 2) k_inc_colors<int16_t><<<vgrid, kBlock, 0, st>>>((int)n, static_cast<const int16_t*>(a.st), a.color);
+    else k_inc_colors<int32_t><<<vgrid, kBlock, 0, st>>>((int)n, static_cast<const int32_t*>(a.st), a.color);
+    GC_CHECK(hipGetLastError());
     if (a.tail > 0) {
         // the vertices the rounds left (at most `tail`), one at a time
         if (width == 1) k_tail_collect<int8_t><<<vgrid, kBlock, 0, st>>>(a);
@@ -3225,6 +3253,8 @@ int run_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
         }
         GC_CHECK(hipGetLastError());
     }
+    k_inc_colors_async<<<vgrid, kBlock, 0, st>>>(n, reinterpret_cast<const int8_t*>(base + Lw.tent),
+                                                 reinterpret_cast<const int32_t*>(base + Lw.told), ctl, colors);
     k_maxcolor<<<grid, kBlock, 0, st>>>(n, colors, ctl);
     k_async_finish<<<1, 64, 0, st>>>(ctl, log, n, (long long)nnz, dlist(budget + 1), stats_dev);
     GC_CHECK(hipGetLastError());
