@@ -191,7 +191,7 @@ int color_graph_async(int32_t n, int64_t nnz, const int32_t* row_ptr, const int3
  * first call there); the caller still passes inputs and outputs as for
  * color_graph_async.  Graphs whose gcolor_workspace_bytes(n, nnz) exceeds the
  * array are refused with GCOLOR_ENOTSUP before any device work (about
- * 342,000 vertices at 10 entries per vertex).  Every call on a device shares
+ * 315,000 vertices at 10 entries per vertex).  Every call on a device shares
  * that device's array, which keeps the last call's contents: calls that
  * overlap on one device (other streams or threads) race and must be
  * serialised by the caller.  Other errors and stats_dev: as

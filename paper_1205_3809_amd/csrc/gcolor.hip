@@ -162,6 +162,9 @@ struct Args {
     int* __restrict__ pref;
     int* __restrict__ pbuf;
     int pcap;
+    // (incremental) per vertex (row start, row end, split point, counter):
+    // the row bounds and split point of a vertex come in one 16-byte load
+    int* __restrict__ vrec;
 };
 
 struct Stage {
@@ -693,6 +696,13 @@ __device__ __forceinline__ bool is_dirty(const unsigned* __restrict__ bits, int 
     return (bits[x >> 5] >> (x & 31)) & 1u;
 }
 
+// Vertex record of the incremental engine: x = row start, y = row end,
+// z = split point, w = counter (conf).
+__device__ __forceinline__ int4 vrec_load(const Args& a, int v) {
+    return reinterpret_cast<const int4*>(a.vrec)[v];
+}
+__device__ __forceinline__ int* vconf(const Args& a, int v) { return a.vrec + 4 * (size_t)v + 3; }
+
 // Round-1 state: every tentative colour is 1, so conf[v] is the number of
 // preceding neighbours; vertices with none are the round-1 candidates.
 // Natural order (rows sorted): split[v] = lower_bound(row, v) - row start.
@@ -726,12 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_inc_seed(Args a, int natural) {
                     else hi = mid;
                 }
                 sp = lo - s;
-                a.split[v] = sp;
             } else {
                 sp = a.split[v];
             }
             st[v] = 1;
-            a.conf[v] = sp;
+            reinterpret_cast<int4*>(a.vrec)[v] = make_int4(s, e, sp, sp);
             a.cflag[v] = 0;
         }
         // heavy rows: an id each (wave-aggregated) and the whole row as the
@@ -891,10 +900,10 @@ __device__ __forceinline__ bool inc_a_eval(const Args& a, const unsigned* __rest
     if (x == w || (sx != now && sx != old)) return false;
     if (is_dirty(bits, x)) return false;
     if (sx == now) {
-        atomicAdd(&a.conf[x], 1);
+        atomicAdd(vconf(a, x), 1);
         return false;
     }
-    if (atomicSub(&a.conf[x], 1) != 1) return false;
+    if (atomicSub(vconf(a, x), 1) != 1) return false;
     return atomicExch(&a.cflag[x], k) != k;
 }
 
@@ -986,8 +995,8 @@ __device__ __forceinline__ void inc_a_eval_staged(const Args& a, WaveStage* stg,
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         r[j] = 0;
-        if (addm >> j & 1u) atomicAdd(&a.conf[xs[j]], 1);
-        else if (subm >> j & 1u) r[j] = atomicSub(&a.conf[xs[j]], 1);
+        if (addm >> j & 1u) atomicAdd(vconf(a, xs[j]), 1);
+        else if (subm >> j & 1u) r[j] = atomicSub(vconf(a, xs[j]), 1);
     }
     unsigned zm = 0u;
 #pragma unroll
@@ -1017,7 +1026,7 @@ struct HeavyView {
     int buf, h;
 };
 
-__device__ __forceinline__ HeavyView heavy_view(const Args& a, int v, int s) {
+__device__ __forceinline__ HeavyView heavy_view(const Args& a, int v, int s, int sp) {
     HeavyView hv;
     hv.h = a.hid[v];
     const int4 r = a.hrow[hv.h];
@@ -1026,7 +1035,7 @@ __device__ __forceinline__ HeavyView heavy_view(const Args& a, int v, int s) {
     hv.buf = r.z;
     hv.row = r.z == 0 ? a.colp : a.act + (size_t)(r.z - 1) * (size_t)a.nnz;
     hv.s0 = s;
-    hv.s1 = s + a.split[v];
+    hv.s1 = s + sp;
     return hv;
 }
 
@@ -1043,12 +1052,12 @@ __device__ __forceinline__ bool hv_keep(int c) { return c < 0 || c > 64 + kFFBit
 // counter and of the preceding-dirty flag, the later neighbours' counter
 // updates (as inc_a_eval), and the compaction of its active row.
 template <int GS, typename S>
-__device__ __forceinline__ void inc_a_heavy(const Args& a, WaveStage* stg, int k, int w, int s, int old, int lig,
+__device__ __forceinline__ void inc_a_heavy(const Args& a, WaveStage* stg, int k, int w, int s, int sp, int old, int lig,
                                             uint64_t* red, int* shc, unsigned* bm, int* cc, int* now_out,
                                             int* cnt_out, bool* dlow_out, int* len_out) {
     S* st = static_cast<S*>(a.st);
     const unsigned* bits = dbits(a, k);
-    const HeavyView hv = heavy_view(a, w, s);
+    const HeavyView hv = heavy_view(a, w, s, sp);
     const int len = hv.pa + hv.la;
     unsigned* F = a.hF + (size_t)hv.h * kFW;
 
@@ -1256,9 +1265,10 @@ __device__ __forceinline__ VInfo load_vinfo(const Args& a, int w) {
     VInfo r;
     r.w = w;
     if (w >= 0) {
-        r.s = a.row_ptr[w];
-        r.e = a.row_ptr[w + 1];
-        r.sp = a.split[w];
+        const int4 q = vrec_load(a, w);
+        r.s = q.x;
+        r.e = q.y;
+        r.sp = q.z;
         r.old = static_cast<const S*>(a.st)[w];
     } else {
         r.s = r.e = r.sp = r.old = 0;
@@ -1291,7 +1301,7 @@ __device__ __forceinline__ void inc_a_vertex_pre(const Args& a, WaveStage* stg, 
             int now, cnt;
             bool dlow;
             int len;
-            inc_a_heavy<GS, S>(a, stg, k, w, s, old, lig, red, shc, bm, cc, &now, &cnt, &dlow, &len);
+            inc_a_heavy<GS, S>(a, stg, k, w, s, vi.sp, old, lig, red, shc, bm, cc, &now, &cnt, &dlow, &len);
             inc_a_finish<GS, S>(a, stg, k, w, e - s, len, lig, now, cnt, dlow, shc, dedges);
             return;
         }
@@ -1383,7 +1393,7 @@ __device__ __forceinline__ void inc_a_finish(const Args& a, WaveStage* stg, int 
     bool to_b = false, cand = false;
     if (lig == 0) {
         st[w] = (S)now;
-        a.conf[w] = cnt;
+        *vconf(a, w) = cnt;
         dedges[0] += deg;
         dedges[1] += scanned;
         to_b = dl > 0;
@@ -1641,10 +1651,11 @@ __device__ __forceinline__ CInfo load_cinfo(const Args& a, int ent) {
     if (ent != INT_MIN) {
         const int v = ent < 0 ? ~ent : ent;
         r.t = static_cast<const S*>(a.st)[v];
-        r.s = a.row_ptr[v];
-        r.e = a.row_ptr[v + 1];
-        r.sp = a.split[v];
-        r.conf = a.conf[v];
+        const int4 q = vrec_load(a, v);
+        r.s = q.x;
+        r.e = q.y;
+        r.sp = q.z;
+        r.conf = q.w;
         r.pref = ent < 0 ? a.pref[v] : -1;
     } else {
         r.t = r.s = r.e = r.sp = r.conf = 0;
@@ -1693,7 +1704,7 @@ __device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& c
             int lim = s + ci.sp;
             if constexpr (GS == kWave) {
                 if (e - s > kHeavyDeg) {  // preceding segment of the active row
-                    const HeavyView hv = heavy_view(a, v, s);
+                    const HeavyView hv = heavy_view(a, v, s, ci.sp);
                     row = hv.row;
                     lim = s + hv.pa;
                 }
@@ -1701,7 +1712,7 @@ __device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& c
             c = group_sum<GS>(inc_b_count<GS, S>(row, st, dbits(a, k), v, s + lig, lim, t));
         }
         const int tot = ci.conf + c;
-        if (lig == 0) a.conf[v] = tot;
+        if (lig == 0) *vconf(a, v) = tot;
         commit = tot == 0;
     } else {
         commit = ci.conf == 0 && t > 0;
@@ -1711,7 +1722,7 @@ __device__ __forceinline__ void inc_c_entry(const Args& a, int k, const CInfo& c
         int start = s + ci.sp, end = e;
         if constexpr (GS == kWave) {
             if (e - s > kHeavyDeg) {  // later segment of the active row
-                const HeavyView hv = heavy_view(a, v, s);
+                const HeavyView hv = heavy_view(a, v, s, ci.sp);
                 row = hv.row;
                 start = hv.s1;
                 end = hv.s1 + hv.la;
@@ -1733,29 +1744,30 @@ __device__ __forceinline__ void inc_c_block(const Args& a, int k, int ent, int* 
     S* st = static_cast<S*>(a.st);
     const int v = ent < 0 ? ~ent : ent;
     const int t = st[v];
-    const int s = a.row_ptr[v], e = a.row_ptr[v + 1];
+    const int4 q = vrec_load(a, v);
+    const int s = q.x, e = q.y, sp = q.z;
     if (ent < 0) {
         const int* row = a.colp;
-        int lim = s + a.split[v];
+        int lim = s + sp;
         if (e - s > kHeavyDeg) {  // preceding segment of the active row
-            const HeavyView hv = heavy_view(a, v, s);
+            const HeavyView hv = heavy_view(a, v, s, sp);
             row = hv.row;
             lim = s + hv.pa;
         }
         const int c = group_sum<kWave>(inc_b_count<kBlock, S>(row, st, dbits(a, k), v, s + (int)threadIdx.x, lim, t));
         if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
         __syncthreads();
-        const int tot = a.conf[v] + sh[0] + sh[1] + sh[2] + sh[3];
-        __syncthreads();  // every thread has read conf[v] and sh
-        if (threadIdx.x == 0) a.conf[v] = tot;
+        const int tot = q.w + sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();  // every thread has read sh
+        if (threadIdx.x == 0) *vconf(a, v) = tot;
         if (tot != 0) return;  // block-uniform
-    } else if (a.conf[v] != 0 || t <= 0) {
+    } else if (q.w != 0 || t <= 0) {
         return;  // block-uniform: only this block writes them in this kernel
     }
     const int* row = a.colp;
-    int start = s + a.split[v], end = e;
+    int start = s + sp, end = e;
     if (e - s > kHeavyDeg) {  // later segment of the active row
-        const HeavyView hv = heavy_view(a, v, s);
+        const HeavyView hv = heavy_view(a, v, s, sp);
         row = hv.row;
         start = hv.s1;
         end = hv.s1 + hv.la;
@@ -2488,7 +2500,7 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t ctl, log, tent, told, conf, cflag, split, lists, dbits, bplane, bcnt, dsum, colp, hid, hrow, hF, act, pref,
-        pbuf, total;
+        pbuf, vrec, total;
 };
 
 // Entries of the pair buffer: one per vertex, at most kPairMaxCap.
@@ -2524,6 +2536,7 @@ Layout layout(int32_t n, int64_t nnz) {
     L.hF = off;    off += align_up(sizeof(uint32_t) * kFW * nh);
     L.act = off;   off += align_up(sizeof(int32_t) * 2 * (size_t)(nnz > 0 ? nnz : 1));
     L.pref = off;  off += align_up(vn);
+    L.vrec = off;  off += align_up(4 * vn);
     L.pbuf = off;  off += align_up(sizeof(int32_t) * (size_t)pair_capacity(n));
     L.total = off;
     return L;
@@ -3041,6 +3054,7 @@ Args make_args(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* co
     a.pref = reinterpret_cast<int*>(base + Lw.pref);
     a.pbuf = reinterpret_cast<int*>(base + Lw.pbuf);
     a.pcap = pair_capacity(n);
+    a.vrec = reinterpret_cast<int*>(base + Lw.vrec);
 
     return a;
 }
