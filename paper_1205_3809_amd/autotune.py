@@ -7,9 +7,9 @@ colours of the starting setting (a mismatch raises).
 * Single graph (color_graph): the four degree-bin limits (one lane, 4 lanes,
   16 lanes and one wavefront per vertex; a workgroup above the last), the
   blocks per CU of the round grids and of the two round kernels, by coordinate
-  descent from the current
-  setting over candidate values, keeping a change only when it is faster by
-  more than the noise margin.
+  descent from the current setting: each coordinate tries all its candidate
+  values and takes the fastest when it beats the current setting by more than
+  the noise margin.
 * Batch (color_graph_batch): threads per workgroup (256 or 1024) and the LDS
   path's vertex capacity (a factor of the batch's mean graph size, capped),
   by exhaustive search over a small grid that includes the LDS path switched
@@ -35,7 +35,7 @@ KERNEL_BLOCK_CANDIDATES = [0, 2, 3, 4, 6, 8, 12]  # per round kernel; 0 = blocks
 BATCH_BLOCKS = [256, 1024]
 BATCH_FACTORS = [2, 4, 8, 16]
 BATCH_CAPS = [16384, 32768, 65536]
-MARGIN = 0.98  # a candidate must be at least 2% faster to replace the current one
+MARGIN = 0.995  # a candidate must be at least 0.5% faster (repeated trials agree within 0.2%)
 
 
 def arch() -> str:
@@ -80,30 +80,53 @@ def tune_single(row_ptr: torch.Tensor, col_idx: torch.Tensor, priority: Optional
     run(cur)
     torch.cuda.synchronize()
     ref = out.clone()
-    t0 = _time_ms(lambda: run(cur), reps)
+
+    def measure(trial):
+        t = _time_ms(lambda: run(trial), reps)
+        if not torch.equal(out, ref):
+            setup(cur)
+            raise RuntimeError("colours changed under tuning %s" % trial)
+        if log:
+            log("tune_single %s: %.3f ms" % (trial, t))
+        return t
+
+    cur, best_t, t0, trials = coordinate_descent(cur, SINGLE_CANDIDATES, measure, passes)
+    setup(cur)
+    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "kernel_blocks": cur[5:7],
+            "ms": round(best_t, 4), "start_ms": round(t0, 4), "trials": trials}
+
+
+SINGLE_CANDIDATES = list(BIN_CANDIDATES) + [BPC_CANDIDATES, KERNEL_BLOCK_CANDIDATES, KERNEL_BLOCK_CANDIDATES]
+
+
+def coordinate_descent(start, candidates, measure, passes=2, margin=MARGIN):
+    """Coordinate descent over the settings (one list of candidate values per
+    coordinate; the first four, the bin limits, must stay non-decreasing):
+    each coordinate tries all its values with the others fixed and takes the
+    fastest of them when it beats the current setting by the noise margin;
+    up to `passes` sweeps, stopping after one that changes nothing.  Returns
+    (setting, its time, the starting time, every trial)."""
+    cur = list(start)
+    t0 = measure(cur)
     best_t, trials = t0, [{"setting": list(cur), "ms": round(t0, 4)}]
     for _ in range(passes):
         changed = False
-        for i in range(7):
-            for v in (BIN_CANDIDATES[i] if i < 4 else BPC_CANDIDATES if i == 4 else KERNEL_BLOCK_CANDIDATES):
+        for i, values in enumerate(candidates):
+            pick, pick_t = None, float("inf")
+            for v in values:
                 trial = list(cur)
                 trial[i] = v
                 if trial == cur or any(trial[j] > trial[j + 1] for j in range(3)):
                     continue
-                t = _time_ms(lambda: run(trial), reps)
-                if not torch.equal(out, ref):
-                    setup(cur)
-                    raise RuntimeError("colours changed under tuning %s" % trial)
+                t = measure(trial)
                 trials.append({"setting": trial, "ms": round(t, 4)})
-                if log:
-                    log("tune_single %s: %.3f ms" % (trial, t))
-                if t < best_t * MARGIN:
-                    best_t, cur, changed = t, trial, True
+                if t < pick_t:
+                    pick, pick_t = trial, t
+            if pick is not None and pick_t < best_t * margin:
+                best_t, cur, changed = pick_t, pick, True
         if not changed:
             break
-    setup(cur)
-    return {"kind": "single", "bin_limits": cur[:4], "blocks_per_cu": cur[4], "kernel_blocks": cur[5:7],
-            "ms": round(best_t, 4), "start_ms": round(t0, 4), "trials": trials}
+    return cur, best_t, t0, trials
 
 
 def tune_batch(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.Tensor, col_idx: torch.Tensor,

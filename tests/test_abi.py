@@ -194,3 +194,33 @@ def test_tuning_table_save_and_apply(tmp_path):
     finally:
         gc.set_tuning(*s_old)
         gc.set_batch_tuning(*b_old)
+
+
+def test_autotuner_search_takes_each_coordinates_best():
+    """The single-graph search on a synthetic timing table: within one
+    coordinate the fastest value wins, not the first that clears the noise
+    margin (the last bin limit: 384 clears it against 2048, 512 is faster
+    still); a value within the margin of the current setting is not taken;
+    the bin limits stay non-decreasing; every measured setting is recorded."""
+    from paper_1205_3809_amd import autotune
+
+    base = {2048: 20.96, 384: 20.40, 512: 20.19, 256: 20.88, 768: 20.25, 1024: 20.26, 4096: 21.5}
+    seen = []
+
+    def measure(s):
+        seen.append(list(s))
+        assert all(s[j] <= s[j + 1] for j in range(3))
+        t = base[s[3]]
+        t += {4: 0.0, 3: -0.05, 2: 1.5}.get(s[4], 3.0)  # blocks per CU: 3 within the margin
+        t += 0.3 * (s[0] != 8) + 0.3 * (s[1] != 32) + 0.3 * (s[2] != 128)
+        t += -0.5 if s[6] == 3 else (0.0 if s[6] == 0 else 2.0)  # commit kernel: 3 per CU clearly faster
+        t += 0.0 if s[5] == 0 else 1.0
+        return t
+
+    cand = [[2, 4, 8, 16], [16, 32, 64], [64, 128, 256], [256, 384, 512, 768, 1024, 2048, 4096], [2, 3, 4],
+            [0, 2, 3], [0, 2, 3]]
+    cur, best, t0, trials = autotune.coordinate_descent([8, 32, 128, 2048, 4, 0, 0], cand, measure, passes=2,
+                                                        margin=0.98)
+    assert cur == [8, 32, 128, 512, 4, 0, 3]
+    assert t0 == pytest.approx(20.96) and best == pytest.approx(20.19 - 0.5)
+    assert [t["setting"] for t in trials] == seen
