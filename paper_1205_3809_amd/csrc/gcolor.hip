@@ -127,11 +127,13 @@ struct Args {
     int n;
     const int* __restrict__ row_ptr;
     const int* __restrict__ colp;  // original col_idx, or the reordered copy
-    int* __restrict__ split;       // entries at the front of each row that precede the vertex
+    int* __restrict__ split;       // entries at the front of each row that precede the vertex (the
+                                   // incremental engine copies them into its vertex records)
     int* __restrict__ color;       // the caller's colors_out (incremental engine: written after the rounds)
     int* __restrict__ tent;        // (plain) tentative colour
     void* st;                      // (incremental) state words, int8_t, int16_t or int32_t
-    int* __restrict__ conf;        // (incremental) preceding worklist neighbours with equal tent
+    int* __restrict__ conf;        // (dataflow) preceding entries still uncoloured; the incremental
+                                   // engine keeps its counters in the vertex records
     int* __restrict__ cflag;       // (incremental) round of last candidate mark
     int* __restrict__ lists;       // [kSets][n], bins at the offsets of their populations
     unsigned* __restrict__ dbits;  // (incremental) 3 dirty bitmaps of nwords words
