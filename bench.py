@@ -734,9 +734,10 @@ def bench_learned(args):
     rp = torch.from_numpy(ev.row_ptr).to(dev)
     ci = torch.from_numpy(ev.col_idx).to(dev)
     out = torch.empty(ev.n, dtype=torch.int32, device=dev)
-    # launch parameters for colouring the evaluation graph (its natural order
-    # stands in for the orders compared here)
-    tuning = apply_tuning(args, "%s-eval" % args.workload, lambda: gc.autotune.tune_single(rp, ci, None, log=log))
+    # launch parameters for colouring the evaluation graph, searched with the
+    # trained model's keys (the order whose end-to-end time is the metric)
+    tuning = apply_tuning(args, "%s-eval" % args.workload,
+                          lambda: gc.autotune.tune_single(rp, ci, L.order_learned(model, rp, ci)[0], log=log))
 
     def timed(fn, reps):
         fn()
