@@ -126,6 +126,36 @@ def test_long_dirty_rows(m, leaves):
     assert col[-1] == m + 1
 
 
+def clique_in_sparse(m, n, pairs, seed):
+    """A clique on 0..m-1 beside a sparse uniform graph on m..n-1: the
+    clique commits one vertex a round, so every round its remaining
+    vertices are dirty with up to m-2 dirty preceding neighbours."""
+    iu, ju = np.triu_indices(m, 1)
+    rng = np.random.default_rng(seed)
+    a = rng.integers(m, n, pairs)
+    b = rng.integers(m, n, pairs)
+    return graphgen.from_pairs(n, np.concatenate([iu, a]), np.concatenate([ju, b]))
+
+
+@pytest.mark.parametrize("blocks_a", [0, 16])
+def test_pair_lists_long_and_overflowing(blocks_a):
+    """The dirty-vertex kernel's pair lists (each dirty vertex's dirty
+    preceding neighbours, written per wavefront region) and both fallbacks to
+    the commit kernel's row rescan: lists longer than 127 (the clique's later
+    vertices, rows of 299 entries held in registers) and regions that fill up
+    (16 workgroups per CU give 16,384 wavefronts, regions of 36 entries for
+    600,000 vertices).  Colours, rounds and log equal the oracle's."""
+    import paper_1205_3809_amd as gc
+    g = clique_in_sparse(300, 600_000, 2_400_000, 5)
+    old = gc.get_kernel_blocks()
+    try:
+        gc.set_kernel_blocks(blocks_a, old[1])
+        col, st = check(g, label="clique+sparse blocks_a=%d" % blocks_a, engines=ENGINES[:1])
+    finally:
+        gc.set_kernel_blocks(*old)
+    assert st.rounds >= 300 and col[:300].max() == 300
+
+
 def dirty_model(g, key=None):
     """Per round: number and degree sum of the worklist vertices whose
     tentative colour differs from the previous round's (the vertices the
