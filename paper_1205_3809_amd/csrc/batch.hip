@@ -401,10 +401,7 @@ __device__ void phase_c_l(const LView& g, int* cnt, int k, int v, int s, int e, 
         if (atomicOr(&nbits[u >> 5], vbit(u)) & vbit(u)) continue;  // marked already
         lpush(g, cnt, dl(k + 1), u);
     }
-    if (lig == 0) {
-        g.color[v] = t;
-        g.st[v] = (int8_t)(-t);
-    }
+    if (lig == 0) g.st[v] = (int8_t)(-t);  // colors_out is written after the last round
 }
 
 // Walk list l[0..m) with groups of GS lanes (vertex i to group tid / GS,
@@ -517,6 +514,11 @@ __device__ void color_one_lds(const BArgs& a, const GView& gg, int gi, int* cnt,
         LDS_PHASE(phase_c_l, nc, g.L(cl(k)));
         __syncthreads();
     }
+    // the rounds end when no vertex is dirty, which happens only once every
+    // vertex has committed (while any is left, the first of a chain of
+    // equal tentative colours commits and its successor becomes dirty): the
+    // colours go out in one coalesced pass from the state words
+    for (int v = tid; v < g.n; v += B) g.color[v] = -(int)g.st[v];
     kout = k;
 }
 
